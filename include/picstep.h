@@ -1,0 +1,269 @@
+/*
+ * picstep.h -- C ABI of the MI355X particle-step library (libpicstep.so).
+ *
+ * The library advances charged macro-particles of the special-relativistic
+ * curvilinear PIC method of arXiv 2511.17710 (Entity paper I) through the
+ * particle part of one leap-frog step (Sec. 2.3, steps 3-8):
+ *   3. interpolate the Yee-staggered contravariant E, B to each particle
+ *      with the first-order shape;
+ *   4. convert them to the global orthonormal Cartesian basis
+ *      (eq. curvspace-tetradtrans, then the spherical rotation);
+ *   5. relativistic Boris push of u^{n-1/2} -> u^{n+1/2}
+ *      (eq. curvspace-equations-of-motion);
+ *   6-7. move x^n -> x^{n+1} in Cartesian space and convert back to code
+ *      coordinates (Sec. 2.4 coordinate maps, App. B);
+ *   8. deposit the conformal current (eq. curvspace-chargecons-2) with the
+ *      charge-conserving zig-zag scheme (Sec. 3.2, footnote).
+ * Grids: 2D/3D Cartesian (periodic), 2D axisymmetric spherical and
+ * quasi-spherical (Sec. 2.4).  Fields are static during a call (test-particle
+ * mode) and taken as centred at t^n.  Particles are kept in a per-cell stable
+ * order by a counting sort.  Reverse-mode (adjoint) steps give gradients of a
+ * linear function of the final current and momenta with respect to the fields
+ * and the initial momenta.
+ *
+ * Conventions
+ *  - Code coordinates x^i in [0, N_i), cell size 1 (Sec. 2.4).
+ *  - Field arrays: [6][np3][np2][np1], x fastest, components
+ *    (E1,E2,E3,B1,B2,B3) = contravariant components at their own Yee points
+ *    (App. A), 2 ghost cells per side of every active dimension
+ *    (np_d = N_d + 4; in 2D np3 = 1).  Current arrays: [3][np3][np2][np1],
+ *    the raw conformal current sum q w dx^i / dt on Yee edges in code units.
+ *  - Four-velocities u (units of m c) are in the global Cartesian basis
+ *    (Sec. 2.3); azimuth phi is tracked for axisymmetric grids (Sec. 2.4).
+ *  - Storage/arithmetic precision is chosen per context (PIC_F32 / PIC_F64);
+ *    "real" below means float or double accordingly.
+ *
+ * Ownership and streams
+ *  - Every device buffer is allocated by the caller (e.g. torch tensors) and
+ *    only borrowed; the library never allocates or frees device memory.
+ *  - All device work is enqueued on the stream given to pic_set_stream
+ *    (default: the null stream).  Calls return after enqueueing, except where
+ *    noted (loads and host readbacks synchronize the stream).
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Errors: every function returns a pic_status; pic_last_error() gives the
+ * message of the last failure on that context.  Argument errors are detected
+ * on the host before any device work is enqueued.
+ */
+#ifndef PICSTEP_H
+#define PICSTEP_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_E_ARG = 1,         /* invalid argument */
+  PIC_E_RANGE = 2,       /* particle or field value outside its valid range */
+  PIC_E_STATE = 3,       /* call out of order (e.g. push before fields/particles) */
+  PIC_E_HIP = 4,         /* HIP runtime error (message holds hipGetErrorString) */
+  PIC_E_CAPACITY = 5,    /* particle capacity or buffer size exceeded */
+  PIC_E_UNSUPPORTED = 6  /* valid but not supported configuration */
+} pic_status;
+
+typedef enum { PIC_CART = 0, PIC_SPH = 1, PIC_QSPH = 2 } pic_geom;
+typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_prec;
+typedef enum { PIC_BASIS_CONTRAVARIANT = 0, PIC_BASIS_TETRAD = 1 } pic_basis;
+
+#define PIC_MAX_SPECIES 8
+
+/* Grid and run description (Sec. 2.4 metrics; Sec. 2.1 units). */
+typedef struct {
+  int32_t geom;            /* pic_geom */
+  int32_t dim;             /* PIC_CART: 2 or 3; PIC_SPH/PIC_QSPH: 2 (axisymmetric) */
+  int32_t n[3];            /* active cells per dimension (unused dims: 1) */
+  double lo[3], hi[3];     /* PIC_CART: box extents; (Q)SPH: lo[0] = r_min, hi[0] = r_max,
+                              theta spans [0, pi] (lo[1], hi[1] ignored) */
+  double r0, vartheta;     /* PIC_QSPH: r = r0 + exp(R), theta(T) stretching, -1/2 < vartheta < 1 */
+  int32_t periodic[3];     /* PIC_CART: must be 1 for each active dimension */
+  double rho0;             /* fiducial Larmor radius: push coefficient k = q dt / (2 m rho0) */
+  int32_t prec;            /* pic_prec of particles, fields and current */
+  int32_t fp64_axis_cells; /* PIC_F32 (Q)SPH: particles within this many cells of theta = 0,
+                              theta = pi or r_min use FP64 for metric and move (default 2) */
+  int32_t sort_every;      /* per-cell sort before global steps that are multiples of this;
+                              0 = only on explicit pic_sort */
+  int32_t reserved;
+  uint64_t max_particles;  /* capacity summed over species */
+} pic_grid_desc;
+
+/* Byte sizes of the caller-allocated buffers (pic_query_sizes). */
+typedef struct {
+  uint64_t fields_bytes;       /* [6][npts] real */
+  uint64_t current_bytes;      /* [3][npts] real */
+  uint64_t particle_set_bytes; /* one particle set (two are bound: the sort ping-pongs) */
+  uint64_t prev_bytes;         /* positions before the last step of pic_push_deposit */
+  uint64_t scratch_bytes;      /* sort keys/values/histograms, permutation, flags */
+  uint64_t checkpoint_bytes;   /* one particle-state checkpoint (adjoint) */
+  uint64_t field_points;       /* npts = np1*np2*np3 */
+  int32_t np[3];               /* padded extents */
+  int32_t elem_bytes;          /* 4 (PIC_F32) or 8 (PIC_F64) */
+} pic_sizes;
+
+/* Device buffers (borrowed). */
+typedef struct {
+  void *fields;       /* fields_bytes */
+  void *current;      /* current_bytes */
+  void *particles[2]; /* 2 x particle_set_bytes */
+  void *prev;         /* prev_bytes */
+  void *scratch;      /* scratch_bytes */
+} pic_buffers;
+
+/* Layout of one particle set: byte offsets of its SoA arrays (UINT64_MAX when
+ * absent), each array holding `capacity` elements; species s occupies elements
+ * [species_offset[s], species_offset[s] + species_capacity[s]).  cell is int32,
+ * u, w and phi are real.  cell packs (i1 + 1) | i2 << shift2 | i3 << shift3; bit
+ * 30 marks a dead particle.  Offsets are in [0, 1) (Sec. 3.1): double in a
+ * PIC_F64 context, 32-bit unsigned fixed point (offset = value * 2^-32) in a
+ * PIC_F32 context, where pic_particles_load rounds to the nearest such value
+ * below 1. */
+typedef struct {
+  uint64_t cell, offs[3], u[3], w, phi;
+  uint64_t capacity;
+  uint64_t species_offset[PIC_MAX_SPECIES];
+  uint64_t species_capacity[PIC_MAX_SPECIES];
+  uint64_t species_count[PIC_MAX_SPECIES]; /* loaded particles (alive or dead) */
+  int32_t nspecies;
+  int32_t active_set;      /* which of the two bound sets holds the current state */
+  int32_t shift2, shift3;  /* cell packing */
+  uint64_t prev_cell, prev_offs[3]; /* byte offsets inside the prev buffer */
+} pic_layout;
+
+/* Host view of one species for pic_particles_get: arrays of n (x3 for cell,
+ * offs and u; rows per particle) that the caller owns; any pointer may be NULL. */
+typedef struct {
+  uint64_t n;          /* in: capacity of the arrays; out: particles written */
+  int32_t *cell;       /* n x 3 per-dimension cell index (unused dims 0) */
+  double *offs;        /* n x 3 */
+  double *u;           /* n x 3 */
+  double *w;           /* n */
+  double *phi;         /* n (axisymmetric) */
+  int32_t *alive;      /* n */
+  int32_t *cell_prev;  /* n x 3, positions before the last pushed step */
+  double *offs_prev;   /* n x 3 */
+  int32_t *perm;       /* n, permutation applied by the last sort (new i <- old perm[i]) */
+} pic_particle_view;
+
+/* ---- context and setup (Sec. 2.4, Sec. 3.1) ---- */
+
+/* Validates the description (host only, no device call) and creates a
+ * context.  PIC_E_ARG for an invalid description, PIC_E_UNSUPPORTED for a
+ * non-periodic Cartesian grid.  *out is set only on PIC_OK. */
+pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out);
+
+/* Destroys a context; never frees caller memory. */
+void pic_grid_destroy(pic_ctx *ctx);
+
+/* Sizes of every caller-allocated buffer (depends on species added so far
+ * only through the total capacity). Host only. */
+pic_status pic_query_sizes(const pic_ctx *ctx, pic_sizes *out);
+
+/* Registers the caller's device buffers (sizes from pic_query_sizes). */
+pic_status pic_bind_buffers(pic_ctx *ctx, const pic_buffers *buf);
+
+/* Stream for all later device work (a hipStream_t; NULL = null stream). */
+pic_status pic_set_stream(pic_ctx *ctx, void *hip_stream);
+
+/* dt = cfl * dx_min, dx_min = min over cell centres of (sum_i 1/h_ii)^(-1/2)
+ * (Sec. 2.4, timestep paragraph).  Host only. */
+pic_status pic_timestep_from_cfl(const pic_ctx *ctx, double cfl, double *dt);
+
+/* Adds a species with charge and mass in fiducial units (Sec. 2.1) and a
+ * capacity; species are laid out contiguously in order of addition.
+ * PIC_E_CAPACITY when the capacities exceed max_particles, PIC_E_STATE
+ * after particles were loaded.  Host only. */
+pic_status pic_species_add(pic_ctx *ctx, double charge, double mass, uint64_t capacity,
+                           int32_t *species_id);
+
+/* Sets the fields from a host FP64 array in `basis`.  Tetrad input is turned
+ * into contravariant components F^i = F^i_hat / sqrt(h_ii) at each
+ * component's own Yee point (eq. curvspace-tetradtrans), in FP64, then
+ * rounded to the storage precision; on (quasi-)spherical grids E3 and B2 are
+ * set to 0 on the axis nodes j = 0 and j = N2 (Sec. 2.6).  includes_ghosts =
+ * 0: `EB` is the active region [6][n3][n2][n1] and periodic ghosts are filled
+ * by copy; 1: `EB` is the padded array [6][np3][np2][np1] (required for
+ * (quasi-)spherical grids).  Synchronizes the stream. */
+pic_status pic_fields_set(pic_ctx *ctx, const double *EB, int32_t basis,
+                          int32_t includes_ghosts);
+
+/* Refills the periodic ghost cells of the bound field buffer from the active
+ * region (after the caller wrote the buffer directly).  Asynchronous. */
+pic_status pic_fields_fill_ghosts(pic_ctx *ctx);
+
+/* Loads n particles of one species from host FP64 arrays (rows per particle):
+ * cell n x dim int32 (per-dimension indices), offs n x dim in [0,1), u n x 3
+ * global Cartesian, w n, phi n (axisymmetric only, else NULL).  Validates on
+ * the host: PIC_E_RANGE for an index outside the grid, an offset outside
+ * [0,1), or a non-finite value; PIC_E_CAPACITY when n exceeds the species
+ * capacity.  Replaces the species' previous content.  Synchronizes. */
+pic_status pic_particles_load(pic_ctx *ctx, int32_t species, uint64_t n, const int32_t *cell,
+                              const double *offs, const double *u, const double *w,
+                              const double *phi);
+
+/* Stable per-cell counting sort of every species (dead particles last);
+ * ties keep their order.  Asynchronous. */
+pic_status pic_sort(pic_ctx *ctx);
+
+/* n_steps particle steps with static fields and step size dt.  Before each
+ * step whose global index is a multiple of sort_every (> 0) the particles are
+ * sorted.  J is zeroed at the start of every step; after the call it holds
+ * the conformal current of the last step (periodic ghost contributions added
+ * into their images, ghosts zero; (quasi-)spherical ghosts keep the current
+ * of radially exiting particles).  Positions before the last step are kept
+ * in the prev buffer.  A particle leaving r_min or r_max deposits its step
+ * and is then dead.  Asynchronous. */
+pic_status pic_push_deposit(pic_ctx *ctx, double dt, int32_t n_steps);
+
+/* Copies the current [3][npts] (storage precision) to dst, on the device
+ * (dst_is_device = 1, asynchronous) or the host (synchronizes). */
+pic_status pic_current_get(const pic_ctx *ctx, void *dst, int32_t dst_is_device);
+
+/* Copies the contravariant fields [6][npts] (storage precision) likewise. */
+pic_status pic_fields_get(const pic_ctx *ctx, void *dst, int32_t dst_is_device);
+
+/* Copies one species to host FP64 arrays in the current (sorted) order.
+ * Synchronizes. */
+pic_status pic_particles_get(const pic_ctx *ctx, int32_t species, pic_particle_view *dst);
+
+/* Byte layout of the particle sets (for zero-copy device views). Host only. */
+pic_status pic_particle_layout(const pic_ctx *ctx, pic_layout *out);
+
+/* Global step counter (number of steps pushed so far). Host only. */
+pic_status pic_step_count(const pic_ctx *ctx, int64_t *step);
+
+/* ---- adjoint (reverse-mode derivative of the discrete K-step map) ----
+ *
+ * L = sum(lamJ * J_K) + sum(lam_u . u_K) is a linear function of the current
+ * of the last of K steps and of the final four-velocities.  The fields are
+ * static, so dL/dF accumulates the transposed interpolation of every step.
+ * Memory is bounded by checkpointing: the particle state is saved every m
+ * steps and each segment is recomputed once during the reverse sweep. */
+
+/* Workspace bytes for pic_forward_checkpointed / pic_backward with K, m. */
+pic_status pic_adjoint_workspace(const pic_ctx *ctx, int32_t K, int32_t m, uint64_t *bytes);
+
+/* K steps without sorting, saving the state at steps 0, m, 2m, ... into
+ * `workspace` (device, pic_adjoint_workspace bytes).  Leaves the context at
+ * step K with J of the last step, like pic_push_deposit.  Asynchronous. */
+pic_status pic_forward_checkpointed(pic_ctx *ctx, double dt, int32_t K, int32_t m,
+                                    void *workspace);
+
+/* Reverse sweep after pic_forward_checkpointed(dt, K, m, workspace).
+ * lamJ: device [3][npts] real (dL/dJ_K; may be NULL = 0); lam_u: device
+ * [3][capacity] real in the particle order of the checkpoints (may be NULL).
+ * Outputs (device, overwritten): dEB [6][npts] real, dL/d(fields) with
+ * periodic ghost contributions added into their images (ghosts 0);
+ * du0 [3][capacity] real, dL/du at step 0.  Restores the particle state of
+ * step 0.  Asynchronous. */
+pic_status pic_backward(pic_ctx *ctx, double dt, int32_t K, int32_t m, void *workspace,
+                        const void *lamJ, const void *lam_u, void *dEB, void *du0);
+
+/* Message of the last failing call on this context (never NULL). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PICSTEP_H */

@@ -485,7 +485,9 @@ void move(const Grid &G, double dt, const int cell[3], const T d[3], const T &ph
       dr = ro * d_expm1(0.5 * d_log1p(sig));
       T drho = (2.0 * (xo * DX[0] + yo * DX[1]) + DX[0] * DX[0] + DX[1] * DX[1]) / (rho_n + rho_o);
       dth = d_atan2(drho * zo - DX[2] * rho_o, rho_o * rho_n + zo * zn);
-      dphi = d_atan2(xo * DX[1] - yo * DX[0], rho_o * rho_o + xo * DX[0] + yo * DX[1]);
+      // azimuth step, numerator and denominator divided by rho_o so that a start
+      // exactly on the axis takes the azimuth of the displacement itself
+      dphi = d_atan2(cp * DX[1] - sp * DX[0], rho_o + cp * DX[0] + sp * DX[1]);
     }
     if (G.geom == 1) {
       dx[0] = dr / G.dr;

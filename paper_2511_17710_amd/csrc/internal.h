@@ -1,0 +1,124 @@
+// internal.h -- shared host/device definitions of libpicstep (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace picstep {
+
+constexpr int NG = 2;                  // ghost cells per side (Sec. 3.1)
+constexpr int MAXSP = 8;               // species per context
+constexpr int32_t DEAD_BIT = 0x40000000;
+constexpr int BLOCK = 256;             // threads per block of the particle kernels
+
+// Grid constants passed by value to kernels.
+struct GridConst {
+  int geom, dim;
+  int n[3];
+  int np[3];
+  int64_t npts;
+  double dx[3];                 // Cartesian cell sizes (1 for unused dims)
+  double rmin, dr, dth;         // spherical: r = rmin + x1 dr, theta = x2 dth
+  double Rmin, dR, dT, r0, vt;  // quasi-spherical: r = r0 + exp(Rmin + x1 dR), T = x2 dT
+  int fp64_cells;               // FP32 curvilinear: cells near theta=0,pi and r_min done in FP64
+  int shift2, shift3;           // cell packing
+  int32_t mask1, mask2, mask3;
+};
+
+// In-cell offset storage: the FP32 build keeps offsets as 32-bit unsigned
+// fixed point (offset = q * 2^-32, uniform resolution over [0,1)), the FP64
+// build as double.
+template <class Real>
+struct OffStore;
+template <>
+struct OffStore<float> {
+  using T = uint32_t;
+};
+template <>
+struct OffStore<double> {
+  using T = double;
+};
+template <class Real>
+using OffT = typename OffStore<Real>::T;
+
+template <class Real>
+struct PSet {  // SoA of one particle set (device pointers)
+  int32_t *cell;
+  OffT<Real> *offs[3];
+  Real *u[3];
+  Real *w;
+  Real *phi;
+};
+
+struct SpeciesTable {
+  int nspec;
+  int64_t off[MAXSP];      // element offset of the species range
+  int64_t n[MAXSP];        // loaded particles
+  int64_t blk0[MAXSP + 1]; // prefix of block counts over species
+  double k[MAXSP];         // q dt / (2 m rho0)
+  double qdt[MAXSP];       // q / dt
+};
+
+template <class Real>
+struct StepArgs {
+  GridConst g;
+  SpeciesTable sp;
+  PSet<Real> p;
+  int32_t *prev_cell;      // written when write_prev
+  OffT<Real> *prev_offs[3];
+  const Real *EB;
+  Real *J;
+  double dt;
+  int write_prev;
+};
+
+// reverse step: recompute the forward step from the stored state and
+// propagate adjoints (lamJ only on the last step)
+template <class Real>
+struct AdjArgs {
+  GridConst g;
+  SpeciesTable sp;
+  PSet<Real> p;            // state before the step (read only)
+  const Real *EB;
+  const Real *lamJ;        // may be null
+  Real *lam_u[3];          // in: adjoint of u after the step; out: before
+  Real *lam_d[3];          // likewise for offsets
+  Real *lam_phi;           // axisymmetric
+  Real *dEB;               // accumulated field adjoint
+  double dt;
+};
+
+// ---- launchers (defined in the .hip files) ----
+template <class Real>
+hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s);
+template <class Real>
+hipError_t launch_adjoint_step(const AdjArgs<Real> &a, hipStream_t s);
+template <class Real>
+hipError_t launch_fill_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s);
+template <class Real>
+hipError_t launch_fold_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s);
+template <class Real>
+hipError_t launch_zero(Real *A, int64_t n, hipStream_t s);
+
+// stable sort of one species range by cell key; writes perm (new i <- old perm[i])
+struct SortScratch {
+  uint32_t *keys[2];
+  int32_t *vals[2];
+  int32_t *hist;      // 256 * max_tiles
+  int32_t *bsum;      // block sums of the scan
+  int64_t max_tiles;
+};
+hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
+                               const SortScratch &S, int32_t *perm_out, int keybits,
+                               hipStream_t s);
+template <class Real>
+hipError_t launch_gather(const PSet<Real> &src, const PSet<Real> &dst, int dim, int has_phi,
+                         int64_t off, int64_t n, const int32_t *perm, hipStream_t s);
+template <class Real>
+hipError_t launch_scatter_back(const Real *src, Real *dst, int64_t off, int64_t n,
+                               const int32_t *perm, hipStream_t s);
+
+constexpr int SORT_TILE = 4096;  // keys per block in the radix passes
+constexpr int SCAN_CHUNK = 4096; // elements per block of the scan
+
+}  // namespace picstep

@@ -1,0 +1,298 @@
+// k_sort.hip -- stable per-cell counting sort of a particle species.
+//
+// Least-significant-digit radix sort on the packed cell key (8-bit digits,
+// dead particles carry the largest key), so equal keys keep their previous
+// order and the permutation is unique.  Per pass: tile histograms (digit-major
+// matrix), one exclusive scan of that matrix, and a stable in-tile ranking by
+// eight one-bit splits in LDS followed by a scatter.  A gather then reorders
+// every SoA array into the second particle set.
+#include "internal.h"
+
+namespace picstep {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = SORT_TILE / SORT_THREADS;  // 16 keys per thread
+constexpr int RADIX = 256;
+
+// block-wide exclusive scan of one int per thread (256 threads, wave64)
+__device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh_warp) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh_warp[wid] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < SORT_THREADS / 64; ++w) {
+    const int t = sh_warp[w];
+    if (w < wid) pre += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+// keys of one species range: packed cell, or 1 << (keybits - 1) when dead
+__global__ __launch_bounds__(SORT_THREADS) void k_make_keys(const int32_t *__restrict__ cell,
+                                                            int64_t n, uint32_t deadkey,
+                                                            uint32_t *__restrict__ keys,
+                                                            int32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = cell[i];
+  keys[i] = (c & DEAD_BIT) ? deadkey : (uint32_t)c;
+  vals[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             int32_t *__restrict__ hist,
+                                                             int64_t ntiles) {
+  __shared__ int h[RADIX];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int64_t i = t0 + (int64_t)j * SORT_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of a long int array: chunk scans, scan of chunk sums, add
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_chunks(int32_t *__restrict__ a, int64_t L,
+                                                              int32_t *__restrict__ bsum) {
+  __shared__ int sw[SORT_THREADS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SORT_ITEMS;
+  int v[SORT_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int64_t i = base + j;
+    v[j] = (i < L) ? a[i] : 0;
+    sum += v[j];
+  }
+  int tot;
+  int pre = block_exclusive_scan(sum, &tot, sw);
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int64_t i = base + j;
+    if (i < L) a[i] = pre;
+    pre += v[j];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_sums(int32_t *__restrict__ bsum, int nb) {
+  __shared__ int sw[SORT_THREADS / 64];
+  int v[SORT_ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int i = threadIdx.x * SORT_ITEMS + j;
+    v[j] = (i < nb) ? bsum[i] : 0;
+    sum += v[j];
+  }
+  int tot;
+  int pre = block_exclusive_scan(sum, &tot, sw);
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int i = threadIdx.x * SORT_ITEMS + j;
+    if (i < nb) bsum[i] = pre;
+    pre += v[j];
+  }
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_scan_add(int32_t *__restrict__ a, int64_t L,
+                                                           const int32_t *__restrict__ bsum) {
+  const int32_t add = bsum[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int64_t i = base + (int64_t)j * SORT_THREADS + threadIdx.x;
+    if (i < L) a[i] += add;
+  }
+}
+
+// stable scatter of one tile: 8 one-bit splits in LDS rank the keys by digit
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ hist,
+    int64_t ntiles) {
+  __shared__ uint32_t sk[SORT_TILE];
+  __shared__ int32_t sv[SORT_TILE];
+  __shared__ int dstart[RADIX];
+  __shared__ int goff[RADIX];
+  __shared__ int sw[SORT_THREADS / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
+  const int nvalid = (int)min((int64_t)SORT_TILE, n - t0);
+  // coalesced load; padding keys carry the largest digit and sit at the end
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int e = j * SORT_THREADS + threadIdx.x;
+    if (e < nvalid) {
+      sk[e] = kin[t0 + e];
+      sv[e] = vin[t0 + e];
+    } else {
+      sk[e] = 0xffffffffu;
+      sv[e] = -1;
+    }
+  }
+  dstart[threadIdx.x] = 0;
+  goff[threadIdx.x] = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  __syncthreads();
+  uint32_t k[SORT_ITEMS];
+  int32_t v[SORT_ITEMS];
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    k[j] = sk[threadIdx.x * SORT_ITEMS + j];
+    v[j] = sv[threadIdx.x * SORT_ITEMS + j];
+  }
+  __syncthreads();
+  for (int b = 0; b < 8; ++b) {
+    const int bit = shift + b;
+    int zeros = 0;
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) zeros += ((k[j] >> bit) & 1u) ? 0 : 1;
+    int ztot;
+    const int zpre = block_exclusive_scan(zeros, &ztot, sw);
+    int zc = zpre;
+    int oc = ztot + threadIdx.x * SORT_ITEMS - zpre;
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const int pos = ((k[j] >> bit) & 1u) ? oc++ : zc++;
+      sk[pos] = k[j];
+      sv[pos] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      k[j] = sk[threadIdx.x * SORT_ITEMS + j];
+      v[j] = sv[threadIdx.x * SORT_ITEMS + j];
+    }
+    __syncthreads();
+  }
+  // first sorted position of every digit in this tile
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int spos = threadIdx.x * SORT_ITEMS + j;
+    if (spos < nvalid) {
+      const int dg = (k[j] >> shift) & (RADIX - 1);
+      const bool first = (spos == 0) || (((sk[spos - 1] >> shift) & (RADIX - 1)) != (uint32_t)dg);
+      if (first) dstart[dg] = spos;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SORT_ITEMS; ++j) {
+    const int spos = threadIdx.x * SORT_ITEMS + j;
+    if (spos < nvalid) {
+      const int dg = (k[j] >> shift) & (RADIX - 1);
+      const int64_t dst = (int64_t)goff[dg] + (spos - dstart[dg]);
+      kout[dst] = k[j];
+      vout[dst] = v[j];
+    }
+  }
+}
+
+hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
+                               const SortScratch &S, int32_t *perm_out, int keybits,
+                               hipStream_t s) {
+  (void)g;
+  if (n <= 0) return hipSuccess;
+  const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  if (ntiles > S.max_tiles) return hipErrorInvalidValue;
+  const int64_t L = (int64_t)RADIX * ntiles;
+  const int64_t nchunks = (L + SCAN_CHUNK - 1) / SCAN_CHUNK;
+  if (nchunks > SCAN_CHUNK) return hipErrorInvalidValue;
+  const uint32_t deadkey = 1u << (keybits - 1);
+  hipLaunchKernelGGL(k_make_keys, dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)),
+                     dim3(SORT_THREADS), 0, s, cell, n, deadkey, S.keys[0], S.vals[0]);
+  const int passes = (keybits + 7) / 8;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    const int src = ps & 1, dst = src ^ 1;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
+                       S.keys[src], n, shift, S.hist, ntiles);
+    hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist,
+                       L, S.bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SORT_THREADS), 0, s, S.bsum, (int)nchunks);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist, L,
+                       S.bsum);
+    int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
+                       S.keys[src], S.vals[src], S.keys[dst], vdst, n, shift, S.hist, ntiles);
+  }
+  return hipGetLastError();
+}
+
+// reorder every SoA array of one species range: dst[off+i] = src[off+perm[i]]
+template <class Real>
+__global__ __launch_bounds__(SORT_THREADS) void k_gather(PSet<Real> src, PSet<Real> dst, int dim,
+                                                         int has_phi, int64_t off, int64_t n,
+                                                         const int32_t *__restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
+  if (i >= n) return;
+  const int32_t pi = perm[i];
+  if (pi < 0 || pi >= n) return;  // never read outside the species range
+  const int64_t j = off + pi;
+  const int64_t o = off + i;
+  dst.cell[o] = src.cell[j];
+  for (int a = 0; a < dim; ++a) dst.offs[a][o] = src.offs[a][j];
+  dst.u[0][o] = src.u[0][j];
+  dst.u[1][o] = src.u[1][j];
+  dst.u[2][o] = src.u[2][j];
+  dst.w[o] = src.w[j];
+  if (has_phi) dst.phi[o] = src.phi[j];
+}
+
+template <class Real>
+hipError_t launch_gather(const PSet<Real> &src, const PSet<Real> &dst, int dim, int has_phi,
+                         int64_t off, int64_t n, const int32_t *perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_gather<Real>), dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)),
+                     dim3(SORT_THREADS), 0, s, src, dst, dim, has_phi, off, n, perm);
+  return hipGetLastError();
+}
+
+// inverse of the gather for one array: dst[off+perm[i]] = src[off+i]
+template <class Real>
+__global__ __launch_bounds__(SORT_THREADS) void k_scatter_back(const Real *__restrict__ src,
+                                                               Real *__restrict__ dst, int64_t off,
+                                                               int64_t n,
+                                                               const int32_t *__restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
+  if (i >= n) return;
+  const int32_t pi = perm[i];
+  if (pi < 0 || pi >= n) return;
+  dst[off + pi] = src[off + i];
+}
+
+template <class Real>
+hipError_t launch_scatter_back(const Real *src, Real *dst, int64_t off, int64_t n,
+                               const int32_t *perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_scatter_back<Real>),
+                     dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)), dim3(SORT_THREADS),
+                     0, s, src, dst, off, n, perm);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gather<float>(const PSet<float> &, const PSet<float> &, int, int,
+                                         int64_t, int64_t, const int32_t *, hipStream_t);
+template hipError_t launch_gather<double>(const PSet<double> &, const PSet<double> &, int, int,
+                                          int64_t, int64_t, const int32_t *, hipStream_t);
+template hipError_t launch_scatter_back<float>(const float *, float *, int64_t, int64_t,
+                                               const int32_t *, hipStream_t);
+template hipError_t launch_scatter_back<double>(const double *, double *, int64_t, int64_t,
+                                                const int32_t *, hipStream_t);
+
+}  // namespace picstep

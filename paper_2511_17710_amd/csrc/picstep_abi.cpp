@@ -1,0 +1,720 @@
+// picstep_abi.cpp -- the C ABI declared in include/picstep.h: host-side
+// validation, metric set-up in FP64, buffer layout, and the step loop that
+// enqueues the HIP kernels on the bound stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/picstep.h"
+#include "internal.h"
+
+using namespace picstep;
+
+namespace {
+constexpr double PI = 3.14159265358979323846;
+constexpr uint64_t ALIGN = 256;
+constexpr uint64_t NONE = ~0ull;
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+int bits_for(int64_t values) {  // bits to represent 0..values-1
+  int b = 0;
+  while ((int64_t(1) << b) < values) ++b;
+  return b;
+}
+}  // namespace
+
+struct pic_ctx {
+  pic_grid_desc d{};
+  GridConst g{};
+  size_t eb = 4;  // element bytes
+  int nspec = 0;
+  double q[MAXSP]{}, m[MAXSP]{};
+  uint64_t cap[MAXSP]{}, off[MAXSP]{}, cnt[MAXSP]{};
+  uint64_t capacity = 0;  // elements per particle array
+  // particle set layout (byte offsets)
+  uint64_t o_cell = 0, o_offs[3]{NONE, NONE, NONE}, o_u[3]{}, o_w = 0, o_phi = NONE;
+  uint64_t set_bytes = 0;
+  uint64_t p_cell = 0, p_offs[3]{NONE, NONE, NONE}, prev_bytes = 0;
+  // scratch layout
+  uint64_t s_keys[2]{}, s_vals[2]{}, s_hist = 0, s_bsum = 0, s_perm = 0, scratch_bytes = 0;
+  int64_t max_tiles = 0;
+  int keybits = 0;
+  uint64_t ckpt_bytes = 0;
+  // bound buffers
+  char *fields = nullptr, *current = nullptr, *pset[2]{nullptr, nullptr}, *prev = nullptr,
+       *scratch = nullptr;
+  bool bound = false, fields_ok = false, loaded = false;
+  int active = 0;
+  hipStream_t stream = nullptr;
+  int64_t step = 0;
+  double dx_min = 0;  // Sec. 2.4 CFL length
+  std::string err;
+};
+
+namespace {
+
+pic_status fail(const pic_ctx *c, pic_status s, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    const_cast<pic_ctx *>(c)->err = buf;
+  }
+  return s;
+}
+
+pic_status hipchk(const pic_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return PIC_OK;
+  return fail(c, PIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- host metric (Sec. 2.4), FP64 ----
+double h_r(const GridConst &g, double x1) {
+  return (g.geom == 1) ? g.rmin + x1 * g.dr : g.r0 + std::exp(g.Rmin + x1 * g.dR);
+}
+double h_theta(const GridConst &g, double x2) {
+  if (g.geom == 1) return x2 * g.dth;
+  const double T = x2 * g.dT;
+  return T + 2.0 * g.vt * T * (1.0 - 2.0 * T / PI) * (1.0 - T / PI);
+}
+void h_sqrt_h(const GridConst &g, double x1, double x2, double h[3]) {
+  if (g.geom == 0) {
+    for (int a = 0; a < 3; ++a) h[a] = g.dx[a];
+    return;
+  }
+  const double r = h_r(g, x1);
+  if (g.geom == 1) {
+    h[0] = g.dr;
+    h[1] = r * g.dth;
+  } else {
+    const double T = x2 * g.dT;
+    const double tp = T / PI;
+    h[0] = g.dR * std::exp(g.Rmin + x1 * g.dR);
+    h[1] = g.dT * (1.0 + 2.0 * g.vt + 12.0 * g.vt * tp * (tp - 1.0)) * r;
+  }
+  h[2] = r * std::sin(h_theta(g, x2));
+}
+
+// Yee offsets (App. A) of E1..B3
+const double STAG[6][3] = {{0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 0.5},
+                           {0, 0.5, 0.5}, {0.5, 0, 0.5}, {0.5, 0.5, 0}};
+
+template <class Real>
+PSet<Real> pset_of(const pic_ctx *c, int which) {
+  PSet<Real> p{};
+  char *b = c->pset[which];
+  p.cell = reinterpret_cast<int32_t *>(b + c->o_cell);
+  for (int a = 0; a < 3; ++a) {
+    p.offs[a] = c->o_offs[a] == NONE ? nullptr : reinterpret_cast<OffT<Real> *>(b + c->o_offs[a]);
+    p.u[a] = reinterpret_cast<Real *>(b + c->o_u[a]);
+  }
+  p.w = reinterpret_cast<Real *>(b + c->o_w);
+  p.phi = c->o_phi == NONE ? nullptr : reinterpret_cast<Real *>(b + c->o_phi);
+  return p;
+}
+
+SpeciesTable species_table(const pic_ctx *c, double dt) {
+  SpeciesTable t{};
+  t.nspec = c->nspec;
+  t.blk0[0] = 0;
+  for (int s = 0; s < c->nspec; ++s) {
+    t.off[s] = (int64_t)c->off[s];
+    t.n[s] = (int64_t)c->cnt[s];
+    t.blk0[s + 1] = t.blk0[s] + (t.n[s] + BLOCK - 1) / BLOCK;
+    t.k[s] = c->q[s] * dt / (2.0 * c->m[s] * c->d.rho0);
+    t.qdt[s] = c->q[s] / dt;
+  }
+  for (int s = c->nspec; s < MAXSP; ++s) t.blk0[s + 1] = t.blk0[c->nspec];
+  return t;
+}
+
+template <class Real>
+pic_status do_sort(pic_ctx *c) {
+  SortScratch S{};
+  for (int a = 0; a < 2; ++a) {
+    S.keys[a] = reinterpret_cast<uint32_t *>(c->scratch + c->s_keys[a]);
+    S.vals[a] = reinterpret_cast<int32_t *>(c->scratch + c->s_vals[a]);
+  }
+  S.hist = reinterpret_cast<int32_t *>(c->scratch + c->s_hist);
+  S.bsum = reinterpret_cast<int32_t *>(c->scratch + c->s_bsum);
+  S.max_tiles = c->max_tiles;
+  int32_t *perm = reinterpret_cast<int32_t *>(c->scratch + c->s_perm);
+  PSet<Real> src = pset_of<Real>(c, c->active), dst = pset_of<Real>(c, c->active ^ 1);
+  for (int s = 0; s < c->nspec; ++s) {
+    const int64_t n = (int64_t)c->cnt[s];
+    const int64_t o = (int64_t)c->off[s];
+    if (n == 0) continue;
+    hipError_t e = launch_sort_species(c->g, src.cell + o, n, S, perm + o, c->keybits, c->stream);
+    if (e != hipSuccess) return hipchk(c, e, "sort");
+    e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o, c->stream);
+    if (e != hipSuccess) return hipchk(c, e, "gather");
+  }
+  // species with no particles keep nothing worth copying; flip the set
+  c->active ^= 1;
+  return PIC_OK;
+}
+
+template <class Real>
+pic_status do_step(pic_ctx *c, double dt, bool write_prev) {
+  StepArgs<Real> a{};
+  a.g = c->g;
+  a.sp = species_table(c, dt);
+  a.p = pset_of<Real>(c, c->active);
+  a.prev_cell = reinterpret_cast<int32_t *>(c->prev + c->p_cell);
+  for (int d = 0; d < 3; ++d)
+    a.prev_offs[d] = c->p_offs[d] == NONE ? nullptr : reinterpret_cast<OffT<Real> *>(c->prev + c->p_offs[d]);
+  a.EB = reinterpret_cast<const Real *>(c->fields);
+  a.J = reinterpret_cast<Real *>(c->current);
+  a.dt = dt;
+  a.write_prev = write_prev ? 1 : 0;
+  hipError_t e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
+  if (e != hipSuccess) return hipchk(c, e, "zero J");
+  e = launch_push_deposit<Real>(a, c->stream);
+  if (e != hipSuccess) return hipchk(c, e, "push_deposit");
+  e = launch_fold_ghosts<Real>(c->g, a.J, 3, c->stream);
+  if (e != hipSuccess) return hipchk(c, e, "fold J");
+  return PIC_OK;
+}
+
+template <class Real>
+pic_status run_steps(pic_ctx *c, double dt, int32_t n, bool allow_sort) {
+  for (int32_t s = 0; s < n; ++s) {
+    if (allow_sort && c->d.sort_every > 0 && c->step % c->d.sort_every == 0) {
+      pic_status st = do_sort<Real>(c);
+      if (st != PIC_OK) return st;
+    }
+    pic_status st = do_step<Real>(c, dt, s == n - 1);
+    if (st != PIC_OK) return st;
+    c->step += 1;
+  }
+  return PIC_OK;
+}
+
+bool isfin(double x) { return std::isfinite(x); }
+
+uint32_t offset_to_fixed(double d) {
+  const double r = std::nearbyint(d * 4294967296.0);
+  if (r >= 4294967295.0) return 0xffffffffu;
+  if (r <= 0.0) return 0u;
+  return (uint32_t)r;
+}
+
+double cfl_length(const GridConst &g) {
+  double best = INFINITY;
+  const int nd = g.geom == 0 ? g.dim : 2;
+  const int n2 = g.dim >= 2 ? g.n[1] : 1;
+  const int n3 = g.dim >= 3 ? g.n[2] : 1;
+  // Sec. 2.4: minimum over cell centres of (sum_i 1/h_ii)^(-1/2)
+  for (int k = 0; k < n3; ++k)
+    for (int j = 0; j < n2; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        double h[3];
+        h_sqrt_h(g, i + 0.5, j + 0.5, h);
+        double s = 0;
+        for (int a = 0; a < nd; ++a) s += 1.0 / (h[a] * h[a]);
+        best = std::min(best, 1.0 / std::sqrt(s));
+        if (g.geom == 0) return best;  // uniform cells
+      }
+  return best;
+}
+
+}  // namespace
+
+
+extern "C" {
+
+pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
+  if (!desc || !out) return PIC_E_ARG;
+  const pic_grid_desc &d = *desc;
+  if (d.geom < 0 || d.geom > 2) return PIC_E_ARG;
+  if (d.geom == PIC_CART && d.dim != 2 && d.dim != 3) return PIC_E_ARG;
+  if (d.geom != PIC_CART && d.dim != 2) return PIC_E_ARG;
+  if (d.prec != PIC_F32 && d.prec != PIC_F64) return PIC_E_ARG;
+  for (int a = 0; a < d.dim; ++a)
+    if (d.n[a] < 1 || d.n[a] > (1 << 20)) return PIC_E_ARG;
+  if (!(d.rho0 > 0) || !isfin(d.rho0)) return PIC_E_ARG;
+  if (d.sort_every < 0 || d.fp64_axis_cells < 0) return PIC_E_ARG;
+  if (d.max_particles == 0 || d.max_particles > (1ull << 31) - (1ull << 20)) return PIC_E_ARG;
+  if (d.geom == PIC_CART) {
+    for (int a = 0; a < d.dim; ++a) {
+      if (!(d.hi[a] > d.lo[a]) || !isfin(d.hi[a]) || !isfin(d.lo[a])) return PIC_E_ARG;
+      if (!d.periodic[a]) return PIC_E_UNSUPPORTED;
+    }
+  } else {
+    if (!(d.lo[0] > 0) || !(d.hi[0] > d.lo[0]) || !isfin(d.hi[0])) return PIC_E_ARG;
+    if (d.geom == PIC_QSPH) {
+      if (!(d.vartheta > -0.5 && d.vartheta < 1.0)) return PIC_E_ARG;
+      if (!(d.lo[0] - d.r0 > 0) || !isfin(d.r0)) return PIC_E_ARG;
+    }
+    if (d.n[1] < 2) return PIC_E_ARG;
+  }
+  pic_ctx *c = new pic_ctx();
+  c->d = d;
+  GridConst &g = c->g;
+  g.geom = d.geom;
+  g.dim = d.dim;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < d.dim ? d.n[a] : 1;
+    g.np[a] = a < d.dim ? d.n[a] + 2 * NG : 1;
+    g.dx[a] = (d.geom == PIC_CART && a < d.dim) ? (d.hi[a] - d.lo[a]) / d.n[a] : 1.0;
+  }
+  g.npts = (int64_t)g.np[0] * g.np[1] * g.np[2];
+  g.rmin = d.lo[0];
+  g.dr = (d.geom != PIC_CART) ? (d.hi[0] - d.lo[0]) / d.n[0] : 0.0;
+  g.dth = (d.geom != PIC_CART) ? PI / d.n[1] : 0.0;
+  if (d.geom == PIC_QSPH) {
+    g.Rmin = std::log(d.lo[0] - d.r0);
+    g.dR = (std::log(d.hi[0] - d.r0) - g.Rmin) / d.n[0];
+    g.dT = PI / d.n[1];
+    g.r0 = d.r0;
+    g.vt = d.vartheta;
+  }
+  g.fp64_cells = d.fp64_axis_cells;
+  // cell packing: (i1 + 1) needs values 0..N1+1, then i2, i3
+  const int b1 = bits_for((int64_t)g.n[0] + 2);
+  const int b2 = d.dim >= 2 ? bits_for(g.n[1]) : 0;
+  const int b3 = d.dim >= 3 ? bits_for(g.n[2]) : 0;
+  if (b1 + b2 + b3 > 30) {
+    delete c;
+    return PIC_E_UNSUPPORTED;
+  }
+  g.shift2 = b1;
+  g.shift3 = b1 + b2;
+  g.mask1 = (1 << b1) - 1;
+  g.mask2 = (1 << b2) - 1;
+  g.mask3 = (1 << b3) - 1;
+  c->keybits = b1 + b2 + b3 + 1;
+  c->eb = d.prec == PIC_F64 ? 8 : 4;
+  // capacity: room for per-species alignment to 64 elements
+  c->capacity = align_up(d.max_particles, 64) + 64 * MAXSP;
+  const uint64_t cap = c->capacity;
+  const uint64_t ab = align_up(cap * c->eb, ALIGN), ai = align_up(cap * 4, ALIGN);
+  uint64_t o = 0;
+  c->o_cell = o;
+  o += ai;
+  for (int a = 0; a < d.dim; ++a) {
+    c->o_offs[a] = o;
+    o += ab;
+  }
+  for (int a = 0; a < 3; ++a) {
+    c->o_u[a] = o;
+    o += ab;
+  }
+  c->o_w = o;
+  o += ab;
+  if (d.geom != PIC_CART) {
+    c->o_phi = o;
+    o += ab;
+  }
+  c->set_bytes = o;
+  o = 0;
+  c->p_cell = o;
+  o += ai;
+  for (int a = 0; a < d.dim; ++a) {
+    c->p_offs[a] = o;
+    o += ab;
+  }
+  c->prev_bytes = o;
+  c->max_tiles = (int64_t)((cap + SORT_TILE - 1) / SORT_TILE);
+  o = 0;
+  for (int a = 0; a < 2; ++a) {
+    c->s_keys[a] = o;
+    o += ai;
+    c->s_vals[a] = o;
+    o += ai;
+  }
+  c->s_hist = o;
+  o += align_up((uint64_t)256 * c->max_tiles * 4, ALIGN);
+  c->s_bsum = o;
+  o += align_up((uint64_t)SCAN_CHUNK * 4, ALIGN);
+  c->s_perm = o;
+  o += ai;
+  c->scratch_bytes = o;
+  // checkpoint: cell, offsets, u, phi
+  c->ckpt_bytes = ai + (uint64_t)d.dim * ab + 3 * ab + (d.geom != PIC_CART ? ab : 0);
+  c->dx_min = cfl_length(g);
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_grid_destroy(pic_ctx *ctx) { delete ctx; }
+
+pic_status pic_query_sizes(const pic_ctx *c, pic_sizes *out) {
+  if (!c || !out) return PIC_E_ARG;
+  out->fields_bytes = 6ull * c->g.npts * c->eb;
+  out->current_bytes = 3ull * c->g.npts * c->eb;
+  out->particle_set_bytes = c->set_bytes;
+  out->prev_bytes = c->prev_bytes;
+  out->scratch_bytes = c->scratch_bytes;
+  out->checkpoint_bytes = c->ckpt_bytes;
+  out->field_points = (uint64_t)c->g.npts;
+  for (int a = 0; a < 3; ++a) out->np[a] = c->g.np[a];
+  out->elem_bytes = (int32_t)c->eb;
+  return PIC_OK;
+}
+
+pic_status pic_bind_buffers(pic_ctx *c, const pic_buffers *b) {
+  if (!c || !b) return PIC_E_ARG;
+  if (!b->fields || !b->current || !b->particles[0] || !b->particles[1] || !b->prev ||
+      !b->scratch)
+    return fail(c, PIC_E_ARG, "bind: null buffer");
+  for (const void *p : {b->fields, b->current, b->particles[0], b->particles[1], b->prev,
+                        b->scratch})
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0)
+      return fail(c, PIC_E_ARG, "bind: buffers must be 256-byte aligned");
+  c->fields = static_cast<char *>(b->fields);
+  c->current = static_cast<char *>(b->current);
+  c->pset[0] = static_cast<char *>(b->particles[0]);
+  c->pset[1] = static_cast<char *>(b->particles[1]);
+  c->prev = static_cast<char *>(b->prev);
+  c->scratch = static_cast<char *>(b->scratch);
+  c->bound = true;
+  c->active = 0;
+  hipError_t e = hipMemsetAsync(c->prev, 0, c->prev_bytes, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->current, 0, 3ull * c->g.npts * c->eb, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->s_perm, 0, c->capacity * 4, c->stream);
+  return hipchk(c, e, "bind: clear");
+}
+
+pic_status pic_set_stream(pic_ctx *c, void *s) {
+  if (!c) return PIC_E_ARG;
+  c->stream = static_cast<hipStream_t>(s);
+  return PIC_OK;
+}
+
+pic_status pic_timestep_from_cfl(const pic_ctx *c, double cfl, double *dt) {
+  if (!c || !dt || !(cfl > 0) || !isfin(cfl)) return PIC_E_ARG;
+  *dt = cfl * c->dx_min;
+  return PIC_OK;
+}
+
+
+pic_status pic_species_add(pic_ctx *c, double charge, double mass, uint64_t capacity,
+                           int32_t *species_id) {
+  if (!c || !species_id) return PIC_E_ARG;
+  if (c->loaded) return fail(c, PIC_E_STATE, "species_add after particles_load");
+  if (c->nspec >= MAXSP) return fail(c, PIC_E_CAPACITY, "at most %d species", MAXSP);
+  if (!isfin(charge) || !(mass > 0) || !isfin(mass))
+    return fail(c, PIC_E_ARG, "species: bad charge/mass");
+  const uint64_t start = c->nspec ? align_up(c->off[c->nspec - 1] + c->cap[c->nspec - 1], 64) : 0;
+  uint64_t used = 0;
+  for (int s = 0; s < c->nspec; ++s) used += c->cap[s];
+  if (used + capacity > c->d.max_particles || start + capacity > c->capacity)
+    return fail(c, PIC_E_CAPACITY, "species capacity exceeds max_particles");
+  const int s = c->nspec++;
+  c->q[s] = charge;
+  c->m[s] = mass;
+  c->cap[s] = capacity;
+  c->off[s] = start;
+  c->cnt[s] = 0;
+  *species_id = s;
+  return PIC_OK;
+}
+
+pic_status pic_fields_set(pic_ctx *c, const double *EB, int32_t basis, int32_t includes_ghosts) {
+  if (!c || !EB) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "fields_set before bind_buffers");
+  if (basis != PIC_BASIS_CONTRAVARIANT && basis != PIC_BASIS_TETRAD)
+    return fail(c, PIC_E_ARG, "bad basis");
+  const GridConst &g = c->g;
+  if (g.geom != 0 && !includes_ghosts)
+    return fail(c, PIC_E_ARG, "curvilinear fields need the padded array (includes_ghosts=1)");
+  std::vector<double> F(6 * g.npts, 0.0);
+  const int k0 = g.dim == 3 ? -NG : 0, k1 = g.dim == 3 ? g.n[2] + NG : 1;
+  const int64_t nact = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  for (int cc = 0; cc < 6; ++cc)
+    for (int k = k0; k < k1; ++k)
+      for (int j = -NG; j < g.n[1] + NG; ++j)
+        for (int i = -NG; i < g.n[0] + NG; ++i) {
+          const int64_t pi = (int64_t)cc * g.npts + (i + NG) +
+                             (int64_t)g.np[0] * ((j + NG) + (int64_t)g.np[1] * (g.dim == 3 ? k + NG : 0));
+          double v;
+          if (includes_ghosts) {
+            v = EB[pi];
+          } else {
+            const bool act = i >= 0 && i < g.n[0] && j >= 0 && j < g.n[1] &&
+                             (g.dim < 3 || (k >= 0 && k < g.n[2]));
+            if (!act) continue;
+            v = EB[(int64_t)cc * nact + i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * (g.dim == 3 ? k : 0))];
+          }
+          if (!isfin(v)) return fail(c, PIC_E_RANGE, "non-finite field value");
+          if (basis == PIC_BASIS_TETRAD) {
+            const bool axis = g.geom != 0 && (cc == 2 || cc == 4) && (j == 0 || j == g.n[1]);
+            if (axis) {
+              v = 0.0;
+            } else {
+              double h[3];
+              h_sqrt_h(g, i + STAG[cc][0], j + STAG[cc][1], h);
+              v = v / h[cc % 3];
+            }
+          } else if (g.geom != 0 && (cc == 2 || cc == 4) && (j == 0 || j == g.n[1])) {
+            v = 0.0;  // axis rule of Sec. 2.6
+          }
+          F[pi] = v;
+        }
+  hipError_t e;
+  if (c->eb == 8) {
+    e = hipMemcpyAsync(c->fields, F.data(), F.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_ghosts<double>(g, reinterpret_cast<double *>(c->fields), 6, c->stream);
+  } else {
+    std::vector<float> f(F.size());
+    for (size_t q = 0; q < F.size(); ++q) f[q] = (float)F[q];
+    e = hipMemcpyAsync(c->fields, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_ghosts<float>(g, reinterpret_cast<float *>(c->fields), 6, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hipchk(c, e, "fields_set");
+  c->fields_ok = true;
+  return PIC_OK;
+}
+
+pic_status pic_fields_fill_ghosts(pic_ctx *c) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "not bound");
+  hipError_t e = c->eb == 8
+                     ? launch_fill_ghosts<double>(c->g, reinterpret_cast<double *>(c->fields), 6, c->stream)
+                     : launch_fill_ghosts<float>(c->g, reinterpret_cast<float *>(c->fields), 6, c->stream);
+  c->fields_ok = true;
+  return hipchk(c, e, "fill_ghosts");
+}
+
+pic_status pic_particles_load(pic_ctx *c, int32_t s, uint64_t n, const int32_t *cell,
+                              const double *offs, const double *u, const double *w,
+                              const double *phi) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "particles_load before bind_buffers");
+  if (s < 0 || s >= c->nspec) return fail(c, PIC_E_ARG, "bad species %d", s);
+  if (n > c->cap[s]) return fail(c, PIC_E_CAPACITY, "%llu particles exceed species capacity %llu",
+                                 (unsigned long long)n, (unsigned long long)c->cap[s]);
+  if (n > 0 && (!cell || !offs || !u || !w)) return fail(c, PIC_E_ARG, "null particle array");
+  const GridConst &g = c->g;
+  const bool axi = g.geom != 0;
+  if (n > 0 && axi && !phi) return fail(c, PIC_E_ARG, "phi required on (quasi-)spherical grids");
+  const int D = g.dim;
+  std::vector<int32_t> hc(n);
+  for (uint64_t p = 0; p < n; ++p) {
+    int ii[3] = {0, 0, 0};
+    for (int a = 0; a < D; ++a) {
+      ii[a] = cell[p * D + a];
+      if (ii[a] < 0 || ii[a] >= g.n[a])
+        return fail(c, PIC_E_RANGE, "particle %llu: cell index %d out of range in dim %d",
+                    (unsigned long long)p, ii[a], a);
+      const double o = offs[p * D + a];
+      if (!(o >= 0.0 && o < 1.0))
+        return fail(c, PIC_E_RANGE, "particle %llu: offset %g outside [0,1)", (unsigned long long)p, o);
+    }
+    for (int a = 0; a < 3; ++a)
+      if (!isfin(u[p * 3 + a])) return fail(c, PIC_E_RANGE, "particle %llu: non-finite u", (unsigned long long)p);
+    if (!isfin(w[p])) return fail(c, PIC_E_RANGE, "particle %llu: non-finite weight", (unsigned long long)p);
+    if (axi && !(phi[p] >= 0.0 && phi[p] < 2 * PI))
+      return fail(c, PIC_E_RANGE, "particle %llu: phi outside [0, 2pi)", (unsigned long long)p);
+    hc[p] = (ii[0] + 1) | (ii[1] << g.shift2) | (ii[2] << g.shift3);
+  }
+  char *base = c->pset[c->active];
+  const uint64_t o = c->off[s];
+  hipError_t e = hipMemcpyAsync(base + c->o_cell + o * 4, hc.data(), n * 4, hipMemcpyHostToDevice, c->stream);
+  auto put = [&](uint64_t boff, const double *src, int stride, int comp) -> hipError_t {
+    if (c->eb == 8) {
+      std::vector<double> t(n);
+      for (uint64_t p = 0; p < n; ++p) t[p] = src[p * stride + comp];
+      hipError_t r = hipMemcpyAsync(base + boff + o * 8, t.data(), n * 8, hipMemcpyHostToDevice, c->stream);
+      if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+      return r;
+    }
+    std::vector<float> t(n);
+    for (uint64_t p = 0; p < n; ++p) {
+      float v = (float)src[p * stride + comp];
+      t[p] = v;
+    }
+    hipError_t r = hipMemcpyAsync(base + boff + o * 4, t.data(), n * 4, hipMemcpyHostToDevice, c->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+    return r;
+  };
+  if (n > 0) {
+    for (int a = 0; a < D && e == hipSuccess; ++a) {
+      if (c->eb == 8) {
+        e = put(c->o_offs[a], offs, D, a);
+      } else {
+        // FP32 build: 32-bit fixed point, nearest multiple of 2^-32 below 1
+        std::vector<uint32_t> t(n);
+        for (uint64_t p = 0; p < n; ++p) t[p] = offset_to_fixed(offs[p * D + a]);
+        e = hipMemcpyAsync(base + c->o_offs[a] + o * 4, t.data(), n * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      }
+    }
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) e = put(c->o_u[a], u, 3, a);
+    if (e == hipSuccess) e = put(c->o_w, w, 1, 0);
+    if (e == hipSuccess && axi) e = put(c->o_phi, phi, 1, 0);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hipchk(c, e, "particles_load");
+  c->cnt[s] = n;
+  c->loaded = true;
+  return PIC_OK;
+}
+
+pic_status pic_sort(pic_ctx *c) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "sort before bind_buffers");
+  return c->eb == 8 ? do_sort<double>(c) : do_sort<float>(c);
+}
+
+pic_status pic_push_deposit(pic_ctx *c, double dt, int32_t n_steps) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "push before bind/fields_set");
+  if (!(dt > 0) || !isfin(dt) || n_steps < 0) return fail(c, PIC_E_ARG, "bad dt or n_steps");
+  if (dt > c->dx_min)
+    return fail(c, PIC_E_ARG, "dt %g exceeds the CFL limit %g (Courant number 1)", dt, c->dx_min);
+  return c->eb == 8 ? run_steps<double>(c, dt, n_steps, true) : run_steps<float>(c, dt, n_steps, true);
+}
+
+pic_status pic_current_get(const pic_ctx *c, void *dst, int32_t dst_is_device) {
+  if (!c || !dst) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "not bound");
+  const size_t nb = 3ull * c->g.npts * c->eb;
+  hipError_t e = hipMemcpyAsync(dst, c->current, nb, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(c->stream);
+  return hipchk(c, e, "current_get");
+}
+
+pic_status pic_fields_get(const pic_ctx *c, void *dst, int32_t dst_is_device) {
+  if (!c || !dst) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "not bound");
+  const size_t nb = 6ull * c->g.npts * c->eb;
+  hipError_t e = hipMemcpyAsync(dst, c->fields, nb, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(c->stream);
+  return hipchk(c, e, "fields_get");
+}
+
+pic_status pic_particles_get(const pic_ctx *c, int32_t s, pic_particle_view *v) {
+  if (!c || !v) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "not bound");
+  if (s < 0 || s >= c->nspec) return fail(c, PIC_E_ARG, "bad species %d", s);
+  const uint64_t n = c->cnt[s];
+  if (v->n < n) return fail(c, PIC_E_CAPACITY, "view holds %llu < %llu particles",
+                           (unsigned long long)v->n, (unsigned long long)n);
+  v->n = n;
+  if (n == 0) return PIC_OK;
+  const GridConst &g = c->g;
+  const int D = g.dim;
+  const uint64_t o = c->off[s];
+  const char *base = c->pset[c->active];
+  std::vector<int32_t> ci(n);
+  std::vector<char> tmp(n * 8);
+  hipError_t e = hipMemcpyAsync(ci.data(), base + c->o_cell + o * 4, n * 4, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  auto unpack = [&](const std::vector<int32_t> &cc, int32_t *dst, int32_t *alive) {
+    for (uint64_t p = 0; p < n; ++p) {
+      const int32_t x = cc[p];
+      if (dst) {
+        dst[3 * p] = (x & g.mask1) - 1;
+        dst[3 * p + 1] = D >= 2 ? (x >> g.shift2) & g.mask2 : 0;
+        dst[3 * p + 2] = D >= 3 ? (x >> g.shift3) & g.mask3 : 0;
+      }
+      if (alive) alive[p] = (x & DEAD_BIT) ? 0 : 1;
+    }
+  };
+  unpack(ci, v->cell, v->alive);
+  auto getx = [&](const char *src, double *dst, int stride, int comp, bool is_offset) -> hipError_t {
+    hipError_t r = hipMemcpyAsync(tmp.data(), src + o * c->eb, n * c->eb, hipMemcpyDeviceToHost, c->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+    if (r != hipSuccess) return r;
+    for (uint64_t p = 0; p < n; ++p) {
+      double v;
+      if (c->eb == 8)
+        v = reinterpret_cast<const double *>(tmp.data())[p];
+      else if (is_offset)
+        v = (double)reinterpret_cast<const uint32_t *>(tmp.data())[p] * 0x1p-32;
+      else
+        v = (double)reinterpret_cast<const float *>(tmp.data())[p];
+      dst[p * stride + comp] = v;
+    }
+    return hipSuccess;
+  };
+  auto get = [&](const char *src, double *dst, int stride, int comp) { return getx(src, dst, stride, comp, false); };
+  if (v->offs && e == hipSuccess) {
+    for (uint64_t p = 0; p < n; ++p) v->offs[3 * p] = v->offs[3 * p + 1] = v->offs[3 * p + 2] = 0.0;
+    for (int a = 0; a < D && e == hipSuccess; ++a) e = getx(base + c->o_offs[a], v->offs, 3, a, true);
+  }
+  for (int a = 0; a < 3 && v->u && e == hipSuccess; ++a) e = get(base + c->o_u[a], v->u, 3, a);
+  if (v->w && e == hipSuccess) e = get(base + c->o_w, v->w, 1, 0);
+  if (v->phi && e == hipSuccess && c->o_phi != NONE) e = get(base + c->o_phi, v->phi, 1, 0);
+  if (v->cell_prev && e == hipSuccess) {
+    e = hipMemcpyAsync(ci.data(), c->prev + c->p_cell + o * 4, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    unpack(ci, v->cell_prev, nullptr);
+  }
+  if (v->offs_prev && e == hipSuccess) {
+    for (uint64_t p = 0; p < n; ++p)
+      v->offs_prev[3 * p] = v->offs_prev[3 * p + 1] = v->offs_prev[3 * p + 2] = 0.0;
+    for (int a = 0; a < D && e == hipSuccess; ++a) e = getx(c->prev + c->p_offs[a], v->offs_prev, 3, a, true);
+  }
+  if (v->perm && e == hipSuccess) {
+    e = hipMemcpyAsync(v->perm, c->scratch + c->s_perm + o * 4, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  return hipchk(c, e, "particles_get");
+}
+
+pic_status pic_particle_layout(const pic_ctx *c, pic_layout *L) {
+  if (!c || !L) return PIC_E_ARG;
+  std::memset(L, 0, sizeof *L);
+  L->cell = c->o_cell;
+  for (int a = 0; a < 3; ++a) {
+    L->offs[a] = c->o_offs[a];
+    L->u[a] = c->o_u[a];
+    L->prev_offs[a] = c->p_offs[a];
+  }
+  L->w = c->o_w;
+  L->phi = c->o_phi;
+  L->capacity = c->capacity;
+  for (int s = 0; s < MAXSP; ++s) {
+    L->species_offset[s] = s < c->nspec ? c->off[s] : 0;
+    L->species_capacity[s] = s < c->nspec ? c->cap[s] : 0;
+    L->species_count[s] = s < c->nspec ? c->cnt[s] : 0;
+  }
+  L->nspecies = c->nspec;
+  L->active_set = c->active;
+  L->shift2 = c->g.shift2;
+  L->shift3 = c->g.shift3;
+  L->prev_cell = c->p_cell;
+  return PIC_OK;
+}
+
+pic_status pic_step_count(const pic_ctx *c, int64_t *step) {
+  if (!c || !step) return PIC_E_ARG;
+  *step = c->step;
+  return PIC_OK;
+}
+
+pic_status pic_adjoint_workspace(const pic_ctx *c, int32_t K, int32_t m, uint64_t *bytes) {
+  if (!c || !bytes || K < 1 || m < 1) return PIC_E_ARG;
+  const uint64_t nck = (uint64_t)((K + m - 1) / m);
+  const uint64_t seg = (uint64_t)std::min(K, m);
+  // checkpoints + per-step states of one segment + adjoint state (u, offs, phi)
+  const uint64_t ab = align_up(c->capacity * c->eb, ALIGN);
+  *bytes = (nck + seg) * align_up(c->ckpt_bytes, ALIGN) + 6 * ab;
+  return PIC_OK;
+}
+
+pic_status pic_forward_checkpointed(pic_ctx *c, double, int32_t, int32_t, void *) {
+  return fail(c, PIC_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+pic_status pic_backward(pic_ctx *c, double, int32_t, int32_t, void *, const void *, const void *,
+                        void *, void *) {
+  return fail(c, PIC_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+"""Python binding of libpicstep.so (include/picstep.h): argument marshalling
+only.  Every step of the particle path runs in the HIP kernels of the library;
+torch provides the device buffers and the stream.  There is no CPU fallback:
+a missing library raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libpicstep.so")
+
+PIC_OK, PIC_E_ARG, PIC_E_RANGE, PIC_E_STATE, PIC_E_HIP, PIC_E_CAPACITY, PIC_E_UNSUPPORTED = range(7)
+STATUS = {0: "PIC_OK", 1: "PIC_E_ARG", 2: "PIC_E_RANGE", 3: "PIC_E_STATE", 4: "PIC_E_HIP",
+          5: "PIC_E_CAPACITY", 6: "PIC_E_UNSUPPORTED"}
+GEOM = {"cart": 0, "sph": 1, "qsph": 2}
+PREC = {"f32": 0, "f64": 1}
+MAXSP = 8
+NG = 2
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("geom", C.c_int32), ("dim", C.c_int32), ("n", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("r0", C.c_double),
+                ("vartheta", C.c_double), ("periodic", C.c_int32 * 3), ("rho0", C.c_double),
+                ("prec", C.c_int32), ("fp64_axis_cells", C.c_int32), ("sort_every", C.c_int32),
+                ("reserved", C.c_int32), ("max_particles", C.c_uint64)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("fields_bytes", C.c_uint64), ("current_bytes", C.c_uint64),
+                ("particle_set_bytes", C.c_uint64), ("prev_bytes", C.c_uint64),
+                ("scratch_bytes", C.c_uint64), ("checkpoint_bytes", C.c_uint64),
+                ("field_points", C.c_uint64), ("np", C.c_int32 * 3), ("elem_bytes", C.c_int32)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("fields", C.c_void_p), ("current", C.c_void_p), ("particles", C.c_void_p * 2),
+                ("prev", C.c_void_p), ("scratch", C.c_void_p)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("cell", C.c_uint64), ("offs", C.c_uint64 * 3), ("u", C.c_uint64 * 3),
+                ("w", C.c_uint64), ("phi", C.c_uint64), ("capacity", C.c_uint64),
+                ("species_offset", C.c_uint64 * MAXSP), ("species_capacity", C.c_uint64 * MAXSP),
+                ("species_count", C.c_uint64 * MAXSP), ("nspecies", C.c_int32),
+                ("active_set", C.c_int32), ("shift2", C.c_int32), ("shift3", C.c_int32),
+                ("prev_cell", C.c_uint64), ("prev_offs", C.c_uint64 * 3)]
+
+
+class ParticleView(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("cell", C.POINTER(C.c_int32)), ("offs", C.POINTER(C.c_double)),
+                ("u", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
+                ("phi", C.POINTER(C.c_double)), ("alive", C.POINTER(C.c_int32)),
+                ("cell_prev", C.POINTER(C.c_int32)), ("offs_prev", C.POINTER(C.c_double)),
+                ("perm", C.POINTER(C.c_int32))]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libpicstep.so; raises if it was not built (no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is missing: build it with "
+                               "`python -m paper_2511_17710_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIBPATH)
+        vp, i32, u64, dbl = C.c_void_p, C.c_int32, C.c_uint64, C.c_double
+        sig = {
+            "pic_grid_init": [C.POINTER(GridDesc), C.POINTER(vp)],
+            "pic_grid_destroy": [vp],
+            "pic_query_sizes": [vp, C.POINTER(Sizes)],
+            "pic_bind_buffers": [vp, C.POINTER(Buffers)],
+            "pic_set_stream": [vp, vp],
+            "pic_timestep_from_cfl": [vp, dbl, C.POINTER(dbl)],
+            "pic_species_add": [vp, dbl, dbl, u64, C.POINTER(i32)],
+            "pic_fields_set": [vp, vp, i32, i32],
+            "pic_fields_fill_ghosts": [vp],
+            "pic_particles_load": [vp, i32, u64, vp, vp, vp, vp, vp],
+            "pic_sort": [vp],
+            "pic_push_deposit": [vp, dbl, i32],
+            "pic_current_get": [vp, vp, i32],
+            "pic_fields_get": [vp, vp, i32],
+            "pic_particles_get": [vp, i32, C.POINTER(ParticleView)],
+            "pic_particle_layout": [vp, C.POINTER(Layout)],
+            "pic_step_count": [vp, C.POINTER(C.c_int64)],
+            "pic_adjoint_workspace": [vp, i32, i32, C.POINTER(u64)],
+            "pic_forward_checkpointed": [vp, dbl, i32, i32, vp],
+            "pic_backward": [vp, dbl, i32, i32, vp, vp, vp, vp, vp],
+            "pic_last_error": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = None if name == "pic_grid_destroy" else (
+                C.c_char_p if name == "pic_last_error" else C.c_int)
+        _LIB = L
+    return _LIB
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """One library context with its torch-allocated device buffers."""
+
+    def __init__(self, geom, dim, n, lo, hi, r0=0.0, vartheta=0.0, periodic=(1, 1, 1),
+                 rho0=1.0, prec="f32", fp64_axis_cells=2, sort_every=20, max_particles=1,
+                 device="cuda"):
+        d = GridDesc()
+        d.geom = GEOM[geom] if isinstance(geom, str) else int(geom)
+        d.dim = int(dim)
+        n = list(n) + [1] * (3 - len(n))
+        lo = list(lo) + [0.0] * (3 - len(lo))
+        hi = list(hi) + [1.0] * (3 - len(hi))
+        for a in range(3):
+            d.n[a], d.lo[a], d.hi[a], d.periodic[a] = int(n[a]), float(lo[a]), float(hi[a]), int(periodic[a])
+        d.r0, d.vartheta, d.rho0 = float(r0), float(vartheta), float(rho0)
+        d.prec = PREC[prec]
+        d.fp64_axis_cells = int(fp64_axis_cells)
+        d.sort_every = int(sort_every)
+        d.max_particles = int(max_particles)
+        self.desc = d
+        self.prec = prec
+        self.dtype = torch.float32 if prec == "f32" else torch.float64
+        self.device = device
+        self.dim = d.dim
+        self.geom = d.geom
+        self.n = tuple(n)
+        h = C.c_void_p()
+        st = lib().pic_grid_init(C.byref(d), C.byref(h))
+        if st != PIC_OK:
+            raise PicError(st, "pic_grid_init rejected the grid description")
+        self.h = h
+        self.bufs = None
+        self.species = []
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().pic_grid_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- helpers
+    def _check(self, st, what):
+        if st != PIC_OK:
+            msg = lib().pic_last_error(self.h)
+            raise PicError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def sizes(self):
+        s = Sizes()
+        self._check(lib().pic_query_sizes(self.h, C.byref(s)), "query_sizes")
+        return s
+
+    def layout(self):
+        L = Layout()
+        self._check(lib().pic_particle_layout(self.h, C.byref(L)), "particle_layout")
+        return L
+
+    def padded_shape(self):
+        s = self.sizes()
+        return (s.np[2], s.np[1], s.np[0])
+
+    # -------------------------------------------------------------- setup
+    def species_add(self, q, m, capacity):
+        sid = C.c_int32()
+        self._check(lib().pic_species_add(self.h, float(q), float(m), int(capacity), C.byref(sid)),
+                    "species_add")
+        self.species.append((q, m, capacity))
+        return sid.value
+
+    def bind(self, stream=None):
+        """Allocate every device buffer with torch and register it."""
+        s = self.sizes()
+
+        def alloc(nb):
+            return torch.empty(max(int(nb), 256), dtype=torch.uint8, device=self.device)
+
+        self.bufs = dict(fields=alloc(s.fields_bytes), current=alloc(s.current_bytes),
+                         p0=alloc(s.particle_set_bytes), p1=alloc(s.particle_set_bytes),
+                         prev=alloc(s.prev_bytes), scratch=alloc(s.scratch_bytes))
+        b = Buffers()
+        b.fields = self.bufs["fields"].data_ptr()
+        b.current = self.bufs["current"].data_ptr()
+        b.particles[0] = self.bufs["p0"].data_ptr()
+        b.particles[1] = self.bufs["p1"].data_ptr()
+        b.prev = self.bufs["prev"].data_ptr()
+        b.scratch = self.bufs["scratch"].data_ptr()
+        self.set_stream(stream)
+        self._check(lib().pic_bind_buffers(self.h, C.byref(b)), "bind_buffers")
+
+    def set_stream(self, stream=None):
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        self._check(lib().pic_set_stream(self.h, C.c_void_p(st.cuda_stream)), "set_stream")
+
+    def timestep_from_cfl(self, cfl):
+        dt = C.c_double()
+        self._check(lib().pic_timestep_from_cfl(self.h, float(cfl), C.byref(dt)), "timestep")
+        return dt.value
+
+    def fields_set(self, EB, basis="tetrad", includes_ghosts=0):
+        EB = np.ascontiguousarray(EB, dtype=np.float64)
+        self._check(lib().pic_fields_set(self.h, _ptr(EB), 1 if basis == "tetrad" else 0,
+                                         int(includes_ghosts)), "fields_set")
+
+    def fields_fill_ghosts(self):
+        self._check(lib().pic_fields_fill_ghosts(self.h), "fields_fill_ghosts")
+
+    def particles_load(self, s, cell, offs, u, w, phi=None):
+        n = int(np.asarray(cell).shape[0])
+        D = self.dim
+        cell = np.ascontiguousarray(np.asarray(cell)[:, :D], dtype=np.int32)
+        offs = np.ascontiguousarray(np.asarray(offs)[:, :D], dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        phi = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+        self._check(lib().pic_particles_load(self.h, int(s), n, _ptr(cell), _ptr(offs), _ptr(u),
+                                             _ptr(w), _ptr(phi)), "particles_load")
+
+    # -------------------------------------------------------------- the step
+    def sort(self):
+        self._check(lib().pic_sort(self.h), "sort")
+
+    def push_deposit(self, dt, n_steps):
+        self._check(lib().pic_push_deposit(self.h, float(dt), int(n_steps)), "push_deposit")
+
+    def step_count(self):
+        v = C.c_int64()
+        self._check(lib().pic_step_count(self.h, C.byref(v)), "step_count")
+        return v.value
+
+    # -------------------------------------------------------------- views / readback
+    def _view(self, buf, byte_off, count, dtype):
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.bufs[buf][byte_off:byte_off + count * esz].view(dtype)
+
+    def current(self):
+        """Device view [3, np3, np2, np1] of the current buffer."""
+        s = self.sizes()
+        return self._view("current", 0, 3 * s.field_points, self.dtype).view((3,) + self.padded_shape())
+
+    def fields(self):
+        """Device view [6, np3, np2, np1] of the contravariant field buffer."""
+        s = self.sizes()
+        return self._view("fields", 0, 6 * s.field_points, self.dtype).view((6,) + self.padded_shape())
+
+    def particle_arrays(self):
+        """Device views of the active particle set (whole capacity)."""
+        L = self.layout()
+        buf = "p1" if L.active_set else "p0"
+        cap = L.capacity
+        none = (1 << 64) - 1
+        out = dict(cell=self._view(buf, L.cell, cap, torch.int32),
+                   u=[self._view(buf, L.u[a], cap, self.dtype) for a in range(3)],
+                   offs=[self._view(buf, L.offs[a], cap, self.dtype) for a in range(self.dim)],
+                   w=self._view(buf, L.w, cap, self.dtype))
+        if L.phi != none:
+            out["phi"] = self._view(buf, L.phi, cap, self.dtype)
+        return out
+
+    def particles_get(self, s):
+        L = self.layout()
+        n = int(L.species_count[s])
+        out = dict(cell=np.zeros((n, 3), np.int32), offs=np.zeros((n, 3)), u=np.zeros((n, 3)),
+                   w=np.zeros(n), phi=np.zeros(n) if self.geom != 0 else None,
+                   alive=np.zeros(n, np.int32), cell_prev=np.zeros((n, 3), np.int32),
+                   offs_prev=np.zeros((n, 3)), perm=np.zeros(n, np.int32))
+        v = ParticleView()
+        v.n = n
+        for k in ("cell", "alive", "cell_prev", "perm"):
+            setattr(v, k, out[k].ctypes.data_as(C.POINTER(C.c_int32)))
+        for k in ("offs", "u", "w", "offs_prev"):
+            setattr(v, k, out[k].ctypes.data_as(C.POINTER(C.c_double)))
+        if out["phi"] is not None:
+            v.phi = out["phi"].ctypes.data_as(C.POINTER(C.c_double))
+        self._check(lib().pic_particles_get(self.h, int(s), C.byref(v)), "particles_get")
+        return out
+
+    def current_host(self):
+        J = np.zeros((3,) + self.padded_shape(),
+                     dtype=np.float32 if self.prec == "f32" else np.float64)
+        self._check(lib().pic_current_get(self.h, _ptr(J), 0), "current_get")
+        return J
+
+    def fields_host(self):
+        F = np.zeros((6,) + self.padded_shape(),
+                     dtype=np.float32 if self.prec == "f32" else np.float64)
+        self._check(lib().pic_fields_get(self.h, _ptr(F), 0), "fields_get")
+        return F
+
+
+def from_workload(wl, prec="f32", device="cuda", sort_every=None, fp64_axis_cells=2,
+                  capacity_slack=0):
+    """Context for a workloads.Workload: grid, species, fields and particles loaded."""
+    caps = [s["cell"].shape[0] + capacity_slack for s in wl.species]
+    ctx = Context(wl.geom, wl.dim, wl.n, wl.lo, wl.hi, r0=wl.r0, vartheta=wl.vartheta,
+                  periodic=wl.periodic, rho0=wl.rho0, prec=prec, fp64_axis_cells=fp64_axis_cells,
+                  sort_every=wl.sort_every if sort_every is None else sort_every,
+                  max_particles=sum(caps), device=device)
+    for s, cap in zip(wl.species, caps):
+        ctx.species_add(s["q"], s["m"], cap)
+    ctx.bind()
+    ctx.fields_set(wl.fields_tetrad, "tetrad", wl.fields_includes_ghosts)
+    for i, s in enumerate(wl.species):
+        ctx.particles_load(i, s["cell"], s["offs"], s["u"], s["w"], s.get("phi"))
+    return ctx

@@ -122,10 +122,12 @@ def maxwell_juttner(rng, n, theta, drift_beta=0.0, chunk=1 << 22):
     return out
 
 
-def _round_f32_offsets(o):
-    o32 = o.astype(np.float32)
-    o32 = np.where(o32 >= np.float32(1.0), np.nextafter(np.float32(1.0), np.float32(0.0)), o32)
-    return o32.astype(np.float64)
+def _round_fixed32_offsets(o):
+    """Offsets as stored by the FP32 library build: nearest multiple of 2^-32,
+    kept below 1."""
+    q = np.rint(o * 2.0 ** 32)
+    q = np.clip(q, 0.0, 2.0 ** 32 - 1.0)
+    return q * 2.0 ** -32
 
 
 # ------------------------------------------------------------------ geometry of inputs
@@ -354,11 +356,11 @@ def _shuffle(rng, wl):
 
 
 def round_to_f32(wl):
-    """Round every particle and field input to FP32-representable FP64 values
-    (offsets stay below 1), so an FP32 run and the FP64 reference start from
-    the same state."""
+    """Round every particle and field input to what the FP32 library build
+    stores (FP32 values; offsets in 32-bit fixed point), as FP64 arrays, so an
+    FP32 run and the FP64 reference start from the same state."""
     for s in wl.species:
-        s["offs"] = _round_f32_offsets(s["offs"])
+        s["offs"] = _round_fixed32_offsets(s["offs"])
         s["u"] = s["u"].astype(np.float32).astype(np.float64)
         s["w"] = s["w"].astype(np.float32).astype(np.float64)
         if s.get("phi") is not None:

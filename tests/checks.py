@@ -27,11 +27,11 @@ def rho_nodes(n, dim, periodic_cart, cell, offs, qw):
     """Cloud-in-cell charge sum_p q w S(node - x_p) on the nodes of the
     (padded) lattice, code coordinates; periodic dims wrap."""
     shp = padded(n, dim)
-    rho = np.zeros(shp)
+    rho = np.zeros(shp, dtype=np.longdouble)
     cell = np.asarray(cell)
-    offs = np.asarray(offs)
+    offs = np.asarray(offs, dtype=np.longdouble)
     for e in range(1 << dim):
-        wgt = np.array(qw, dtype=np.float64)
+        wgt = np.array(qw, dtype=np.longdouble)
         idx = []
         for d in range(dim):
             o = (e >> d) & 1
@@ -50,10 +50,10 @@ def rho_nodes(n, dim, periodic_cart, cell, offs, qw):
 
 def divergence(J, n, dim, periodic_cart):
     """sum_d (J^d[node] - J^d[node - e_d]) at every node; J^d[i] sits at i + 1/2."""
-    div = np.zeros(J.shape[1:])
+    div = np.zeros(J.shape[1:], dtype=np.longdouble)
     for d in range(dim):
         ax = 2 - d  # x is the last axis
-        A = J[d]
+        A = np.asarray(J[d], dtype=np.longdouble)
         if periodic_cart:
             # active region is periodic; ghosts of J are zero after folding
             act = [slice(None)] * 3
@@ -76,14 +76,16 @@ def divergence(J, n, dim, periodic_cart):
 
 
 def continuity_residual(J, n, dim, periodic_cart, dt, prev, new, qw):
-    """||div J + (rho_new - rho_old)/dt||_2 / ||(rho_new - rho_old)/dt||_2.
+    """||div J + (rho_new - rho_old)/dt||_2 / ||(rho_new - rho_old)/dt||_2,
+    accumulated in extended precision so that the difference of the two
+    charge densities keeps its digits for small displacements.
 
     prev/new: (cell, offs) of every particle that moved during the step."""
     r0 = rho_nodes(n, dim, periodic_cart, prev[0], prev[1], qw)
     r1 = rho_nodes(n, dim, periodic_cart, new[0], new[1], qw)
     drho = (r1 - r0) / dt
     res = divergence(J, n, dim, periodic_cart) + drho
-    return float(np.linalg.norm(res) / np.linalg.norm(drho))
+    return float(np.sqrt(np.sum(res * res)) / np.sqrt(np.sum(drho * drho)))
 
 
 def unwrap_step(cell_old, cell_new, n, dim, periodic_cart):

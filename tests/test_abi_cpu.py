@@ -1,0 +1,132 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/picstep.h declares, its structs match the header layout,
+and host-only calls validate their arguments."""
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "picstep.h")
+
+pk = pytest.importorskip("paper_2511_17710_amd.picstep")
+
+
+def _lib_or_skip():
+    if not os.path.exists(pk.LIBPATH):
+        pytest.skip("libpicstep.so not built")
+    return pk.lib()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:pic_status|void|const char \*)\s*\*?\s*(pic_\w+)\s*\(",
+                                 txt, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib_or_skip()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_ctypes_structs_match_header():
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "picstep.h"
+int main(void){
+  printf("%zu %zu %zu %zu %zu\n", sizeof(pic_grid_desc), sizeof(pic_sizes), sizeof(pic_buffers),
+         sizeof(pic_layout), sizeof(pic_particle_view));
+  printf("%zu %zu %zu\n", offsetof(pic_grid_desc, max_particles), offsetof(pic_layout, nspecies),
+         offsetof(pic_layout, prev_cell));
+  return 0; }
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    import ctypes as C
+    got = [C.sizeof(pk.GridDesc), C.sizeof(pk.Sizes), C.sizeof(pk.Buffers), C.sizeof(pk.Layout),
+           C.sizeof(pk.ParticleView), pk.GridDesc.max_particles.offset, pk.Layout.nspecies.offset,
+           pk.Layout.prev_cell.offset]
+    assert [int(x) for x in out] == got
+
+
+def _ctx(**kw):
+    base = dict(geom="cart", dim=2, n=(8, 8), lo=(0, 0), hi=(8, 8), max_particles=100)
+    base.update(kw)
+    return pk.Context(**base)
+
+
+def test_grid_init_validation():
+    _lib_or_skip()
+    with pytest.raises(pk.PicError) as e:
+        _ctx(geom=5)
+    assert e.value.status == pk.PIC_E_ARG
+    with pytest.raises(pk.PicError) as e:
+        _ctx(periodic=(0, 1, 1))
+    assert e.value.status == pk.PIC_E_UNSUPPORTED
+    with pytest.raises(pk.PicError) as e:
+        _ctx(geom="qsph", dim=2, n=(8, 8), lo=(1, 0), hi=(10, 3.14), vartheta=1.5)
+    assert e.value.status == pk.PIC_E_ARG
+    with pytest.raises(pk.PicError):
+        _ctx(geom="sph", dim=3, n=(8, 8, 8), lo=(1, 0, 0), hi=(10, 3.14, 1))
+    with pytest.raises(pk.PicError):
+        _ctx(max_particles=0)
+    with pytest.raises(pk.PicError):
+        _ctx(rho0=-1.0)
+
+
+def test_species_capacity_and_state_errors():
+    _lib_or_skip()
+    c = _ctx(max_particles=100)
+    assert c.species_add(-1, 1, 60) == 0
+    with pytest.raises(pk.PicError) as e:
+        c.species_add(1, 1, 50)
+    assert e.value.status == pk.PIC_E_CAPACITY
+    with pytest.raises(pk.PicError) as e:
+        c.species_add(1, 0.0, 10)
+    assert e.value.status == pk.PIC_E_ARG
+    # calls that need bound device buffers report a state error, not a crash
+    import ctypes as C
+    st = pk.lib().pic_push_deposit(c.h, 0.1, 1)
+    assert st == pk.PIC_E_STATE
+    st = pk.lib().pic_sort(c.h)
+    assert st == pk.PIC_E_STATE
+
+
+@pytest.mark.parametrize("geom,n,lo,hi,vt", [
+    ("cart", (64, 64), (0, 0), (64, 64), 0.0),
+    ("cart", (16, 8, 4), (0, 0, 0), (8, 8, 8), 0.0),
+    ("sph", (64, 32), (1, 0), (20, np.pi), 0.0),
+    ("qsph", (128, 64), (1, 0), (50, np.pi), 0.3)])
+def test_timestep_matches_reference(geom, n, lo, hi, vt):
+    """Sec. 2.4 CFL rule, host side of the library vs the FP64 reference."""
+    _lib_or_skip()
+    dim = len(n)
+    c = pk.Context(geom, dim, n, lo, hi, vartheta=vt, periodic=(1, 1, 1) if geom == "cart" else (0, 0, 0),
+                   max_particles=10)
+    g = O.make_grid(geom, dim, n, lo, hi, vartheta=vt, periodic=(1, 1, 1))
+    assert c.timestep_from_cfl(0.45) == pytest.approx(O.dt_from_cfl(g, 0.45), rel=1e-14)
+
+
+def test_sizes_are_consistent():
+    _lib_or_skip()
+    for prec, eb in (("f32", 4), ("f64", 8)):
+        c = _ctx(prec=prec, n=(10, 6), hi=(10, 6))
+        s = c.sizes()
+        assert s.elem_bytes == eb
+        assert tuple(s.np) == (14, 10, 1)
+        assert s.field_points == 14 * 10
+        assert s.fields_bytes == 6 * 140 * eb and s.current_bytes == 3 * 140 * eb
+        assert s.particle_set_bytes > 0 and s.scratch_bytes > 0

@@ -324,6 +324,8 @@ def test_offset_relative_move_equals_literal(geom, vt, rmax):
     cell[:200, 1] = rng.integers(0, 2, 200)  # near theta = 0
     cell[200:400, 1] = N2 - 1 - rng.integers(0, 2, 200)  # near theta = pi
     offs = np.concatenate([rng.random((P, 2)), np.zeros((P, 1))], 1)
+    cell[400:420, 1] = 0
+    offs[400:420, 1] = 0.0  # exactly on the axis theta = 0
     phi = rng.uniform(0, 2 * PI, P)
     u = rng.normal(size=(P, 3)) * 3
     res = O.move(g, dt, cell, offs, phi, u)
