@@ -1,0 +1,178 @@
+"""Benchmark of the particle step (interpolate, rotate, Boris push, zig-zag
+deposit, per-cell sort every 20 steps) on one MI355X.
+
+Default workload: 3D Cartesian 128^3 periodic box, two species with 16
+particles per cell each (67,108,864 particles), Maxwell-Juttner theta=1 with a
+0.3c drift, B0 = 1 z plus 32 seeded plane waves (synthetic, seeded inputs).
+
+Prints one JSON line: ns per particle per step of the FP32 library (value),
+the FP64 form beside it, the roofline of the fused particle-step kernel
+(algorithmic HBM bytes per launch over its HIP-event duration), and the FP64
+CPU reference timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes_per_particle(dim, prec, ncells, nparticles, has_phi=False):
+    """Minimum HBM traffic of one particle step: the particle SoA read (cell,
+    offsets, u, w, phi) and written (cell, offsets, u, phi), the fields read
+    once per cell and the current read-modify-written once per cell."""
+    b = 4 if prec == "f32" else 8
+    ob = 4 if prec == "f32" else 8  # FP32 build: 32-bit fixed-point offsets
+    rd = 4 + dim * ob + 3 * b + b + (b if has_phi else 0)
+    wr = 4 + dim * ob + 3 * b + (b if has_phi else 0)
+    grid = (6 * b + 2 * 3 * b) * ncells / nparticles
+    return rd + wr + grid
+
+
+def run_gpu(wl, prec, steps, warmup, log):
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    t0 = time.time()
+    ctx = P.from_workload(wl, prec=prec)
+    dt = ctx.timestep_from_cfl(wl.cfl)
+    torch.cuda.synchronize()
+    log(f"[bench] {prec}: loaded {wl.nparticles} particles in {time.time() - t0:.1f}s, dt={dt:.6g}")
+    ctx.push_deposit(dt, warmup)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    s = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    ctx.push_deposit(dt, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tm = ctx.timing_read()
+    ctx.timing_enable(False)
+    n = wl.nparticles
+    res = dict(ms_per_step=ms / steps, ns_per_particle_step=ms * 1e6 / (n * steps),
+               push_ms_avg=tm["push_ms"] / max(tm["push_launches"], 1),
+               push_launches=tm["push_launches"], sort_ms_total=tm["sort_ms"],
+               sort_calls=tm["sort_calls"],
+               tile_fallback_frac=round(tm["push_fallback_blocks"] / max(tm["push_blocks"], 1), 5))
+    log(f"[bench] {prec}: {res}")
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(wl, sample_per_species, steps, log):
+    """FP64 CPU reference (single thread) on the first particles of each species."""
+    from oracle import oracle as O
+    g = O.make_grid(wl.geom, wl.dim, wl.n, wl.lo, wl.hi, r0=wl.r0, vartheta=wl.vartheta,
+                    periodic=wl.periodic, rho0=wl.rho0)
+    EB = O.fields_from_tetrad(g, wl.fields_tetrad, wl.fields_includes_ghosts)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    sub = []
+    for s in wl.species:
+        k = min(sample_per_species, s["cell"].shape[0])
+        sub.append({key: (v[:k] if isinstance(v, np.ndarray) else v) for key, v in s.items()})
+    n = sum(x["cell"].shape[0] for x in sub)
+    t0 = time.perf_counter()
+    O.run(g, dt, steps, EB, sub, sort_every=wl.sort_every)
+    el = time.perf_counter() - t0
+    log(f"[bench] cpu reference: {n} particles x {steps} steps in {el:.1f}s")
+    return dict(value=el * 1e9 / (n * steps), unit="ns/particle/step", cores=1, kind="oracle",
+                sample=f"first {sample_per_species} particles of each of the 2 species of "
+                       f"{wl.name} ({n} particles) x {steps} steps incl. the step-0 sort, "
+                       f"FP64, single thread, host {os.uname().machine} nproc={os.cpu_count()}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cart3d_128")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs the particle step on one GPU only; "
+                                   "multi-GPU domain decomposition is a design note, not built",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_2511_17710_amd import workloads as W
+    t0 = time.time()
+    wl = W.by_name(args.workload)
+    log(f"[bench] inputs {wl.name}: {wl.nparticles} particles in {time.time() - t0:.1f}s")
+    ncells = int(np.prod(wl.n[:wl.dim]))
+    has_phi = wl.geom != "cart"
+
+    if args.calib_copy_mb:
+        nb = args.calib_copy_mb << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
+
+    r32 = run_gpu(wl, "f32", args.steps, args.warmup, log)
+    r64 = None if args.skip_fp64 else run_gpu(wl, "f64", args.steps, args.warmup, log)
+    cpu = None if args.skip_cpu else cpu_baseline(wl, args.cpu_sample, args.cpu_steps, log)
+
+    n = wl.nparticles
+    bpp32 = algorithmic_bytes_per_particle(wl.dim, "f32", ncells, n, has_phi)
+    ach = bpp32 * n / (r32["push_ms_avg"] * 1e-3) / 1e9
+    kname = "k_push<%d,%d,float>" % ({"cart": 0, "sph": 1, "qsph": 2}[wl.geom], wl.dim)
+    out = {
+        "metric": "ns/particle/step push+deposit (fwd, adjoint) FP32 vs FP64; HBM GB/s vs peak",
+        "value": round(r32["ns_per_particle_step"], 5),
+        "unit": "ns/particle/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.n[:wl.dim]), "particles": n,
+                   "species": len(wl.species), "sort_every": wl.sort_every, "cfl": wl.cfl,
+                   "offsets": "u32 fixed point (f32 build)"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": kname,
+                     "bytes_per_particle": round(bpp32, 3),
+                     "kernel_ms_avg": round(r32["push_ms_avg"], 4)},
+        "fp32": r32,
+    }
+    if r64:
+        bpp64 = algorithmic_bytes_per_particle(wl.dim, "f64", ncells, n, has_phi)
+        r64["achieved_GBs"] = round(bpp64 * n / (r64["push_ms_avg"] * 1e-3) / 1e9, 1)
+        out["fp64"] = r64
+        out["fp32_vs_fp64_speedup"] = round(r64["ns_per_particle_step"] / r32["ns_per_particle_step"], 3)
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -233,6 +233,24 @@ pic_status pic_particle_layout(const pic_ctx *ctx, pic_layout *out);
 /* Global step counter (number of steps pushed so far). Host only. */
 pic_status pic_step_count(const pic_ctx *ctx, int64_t *step);
 
+/* Kernel timing.  While enabled, HIP events recorded on the bound stream
+ * bracket every launch of the fused particle-step kernel, every per-cell sort
+ * and every adjoint step kernel.  pic_timing_read waits for the recorded
+ * events, returns the accumulated times (ms) and launch counts, and clears
+ * them. */
+typedef struct {
+  int64_t push_launches;
+  double push_ms;
+  int64_t sort_calls;
+  double sort_ms;
+  int64_t adjoint_launches;
+  double adjoint_ms;
+  int64_t push_blocks;           /* blocks of the fused kernel with live particles */
+  int64_t push_fallback_blocks;  /* of which deposited with global atomics (box > LDS tile) */
+} pic_timing;
+pic_status pic_timing_enable(pic_ctx *ctx, int32_t enable);
+pic_status pic_timing_read(pic_ctx *ctx, pic_timing *out);
+
 /* ---- adjoint (reverse-mode derivative of the discrete K-step map) ----
  *
  * L = sum(lamJ * J_K) + sum(lam_u . u_K) is a linear function of the current

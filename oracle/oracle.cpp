@@ -725,10 +725,21 @@ PlainSpecies copy_in(const Grid &G, const orc_species &s) {
   return p;
 }
 
+// Sort key: cells ordered brick by brick (4x4x4 bricks in 3D, 8x8 in 2D), x
+// fastest between and inside bricks, so that a run of consecutive particles
+// covers a compact block of cells; dead particles last.
 int32_t sort_key(const Grid &G, const int32_t *c, int32_t alive) {
   if (!alive) return INT32_MAX;
-  int64_t key = c[0] + (int64_t)G.n[0] * (c[1] + (int64_t)G.n[1] * c[2]);
-  return (int32_t)key;
+  const int B[3] = {G.dim == 3 ? 4 : 8, G.dim == 3 ? 4 : 8, G.dim == 3 ? 4 : 1};
+  int nb[3], bi[3], li[3];
+  for (int d = 0; d < 3; ++d) {
+    nb[d] = (G.n[d] + B[d] - 1) / B[d];
+    bi[d] = c[d] / B[d];
+    li[d] = c[d] % B[d];
+  }
+  const int64_t brick = bi[0] + (int64_t)nb[0] * (bi[1] + (int64_t)nb[1] * bi[2]);
+  const int64_t local = li[0] + (int64_t)B[0] * (li[1] + (int64_t)B[1] * li[2]);
+  return (int32_t)(brick * (B[0] * B[1] * B[2]) + local);
 }
 
 }  // namespace
@@ -909,7 +920,8 @@ void orc_sort_perm(int64_t n, const int32_t *keys, int32_t *perm) {
 }
 
 // K steps of the particle step for every species (fields static).  Before step s
-// (global index step0+s) the particles are stably sorted by cell when
+// (global index step0+s) the particles are stably sorted by cell (brick order,
+// see sort_key) when
 // sort_every > 0 and (step0+s) % sort_every == 0; dead particles go last.
 // J is zeroed at the start of each step; after the call it holds the current of
 // the last step.  prev positions are recorded on the last step.

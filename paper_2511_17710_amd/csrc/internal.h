@@ -10,6 +10,7 @@ constexpr int NG = 2;                  // ghost cells per side (Sec. 3.1)
 constexpr int MAXSP = 8;               // species per context
 constexpr int32_t DEAD_BIT = 0x40000000;
 constexpr int BLOCK = 256;             // threads per block of the particle kernels
+constexpr int PUSH_CHUNK = 1024;       // particles per block of the fused step kernel
 
 // Grid constants passed by value to kernels.
 struct GridConst {
@@ -23,6 +24,8 @@ struct GridConst {
   int fp64_cells;               // FP32 curvilinear: cells near theta=0,pi and r_min done in FP64
   int shift2, shift3;           // cell packing
   int32_t mask1, mask2, mask3;
+  int brick[3];                 // sort order: cells brick by brick (4^3 in 3D, 8^2 in 2D)
+  int nbrick[3];
 };
 
 // In-cell offset storage: the FP32 build keeps offsets as 32-bit unsigned
@@ -70,6 +73,7 @@ struct StepArgs {
   Real *J;
   double dt;
   int write_prev;
+  int32_t *stats;          // [0]: blocks, [1]: blocks that deposited with global atomics
 };
 
 // reverse step: recompute the forward step from the stored state and

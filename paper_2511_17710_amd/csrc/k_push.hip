@@ -1,44 +1,133 @@
 // k_push.hip -- fused particle step: interpolate, rotate, Boris, move, deposit
-// (arXiv 2511.17710, Sec. 2.3 steps 3-8), one thread per particle, one launch
-// for all species.
+// (arXiv 2511.17710, Sec. 2.3 steps 3-8), one launch for all species.
+//
+// A block owns CHUNK consecutive particles of one species (4 per thread,
+// loaded with 16-byte vector accesses).  Particles are kept in brick order by
+// the per-cell sort, so the chunk's cells form a compact box: the block
+// privatises the current of that box (plus the stencil halo) in LDS,
+// accumulates with LDS atomics, and flushes every nonzero tile value with one
+// global atomic.  When the box outgrows the tile (particles drifted far since
+// the last sort, or wrapped across a periodic boundary) the block deposits
+// with global atomics instead; both paths give the same sums.
 #include "step_device.h"
 
 namespace picstep {
 
-// ---------------------------------------------------------------- Cartesian grids
-// Tetrad on a Cartesian grid: F^i_hat = Delta_i F^i (eq. curvspace-tetradtrans,
-// Sec. 2.4 Cartesian metric; h33 = 1 in 2D); the basis is already global.
+constexpr int PPT = 4;                  // particles per thread
+constexpr int CHUNK = PUSH_CHUNK;       // particles per block
+static_assert(BLOCK * PPT == CHUNK, "chunk layout");
+constexpr int TILE_BYTES = 32768;       // LDS current tile per block
+
+// ---------------------------------------------------------------- vector I/O
+__device__ __forceinline__ void ld4(const float *p, float v[4]) {
+  const float4 x = *reinterpret_cast<const float4 *>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void ld4(const uint32_t *p, uint32_t v[4]) {
+  const uint4 x = *reinterpret_cast<const uint4 *>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void ld4(const int32_t *p, int32_t v[4]) {
+  const int4 x = *reinterpret_cast<const int4 *>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double v[4]) {
+  const double2 a = *reinterpret_cast<const double2 *>(p);
+  const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void st4(float *p, const float v[4]) {
+  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(uint32_t *p, const uint32_t v[4]) {
+  *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(int32_t *p, const int32_t v[4]) {
+  *reinterpret_cast<int4 *>(p) = make_int4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(double *p, const double v[4]) {
+  *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+  *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+}
+
+template <class T>
+__device__ __forceinline__ void load_n(const T *p, int cnt, T v[4], T fill) {
+  if (cnt == PPT) {
+    ld4(p, v);
+  } else {
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) v[r] = (r < cnt) ? p[r] : fill;
+  }
+}
+template <class T>
+__device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
+  if (cnt == PPT) {
+    st4(p, v);
+  } else {
+#pragma unroll
+    for (int r = 0; r < PPT; ++r)
+      if (r < cnt) p[r] = v[r];
+  }
+}
+
+// ---------------------------------------------------------------- block -> chunk
+__device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0) {
+  const int64_t b = blockIdx.x;
+  s = 0;
+#pragma unroll
+  for (int t = 1; t < MAXSP; ++t)
+    if (t < sp.nspec && b >= sp.blk0[t]) s = t;
+  c0 = (b - sp.blk0[s]) * CHUNK;
+  return c0 < sp.n[s];
+}
+
+// block-wide min/max of three ints (256 threads)
+__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red[w * 6 + d] = lo[d];
+      red[w * 6 + 3 + d] = hi[d];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = red[d];
+    hi[d] = red[3 + d];
+#pragma unroll
+    for (int ww = 1; ww < BLOCK / 64; ++ww) {
+      lo[d] = min(lo[d], red[ww * 6 + d]);
+      hi[d] = max(hi[d], red[ww * 6 + 3 + d]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- per-particle steps
+// Cartesian: tetrad F^i_hat = Delta_i F^i (eq. curvspace-tetradtrans with the
+// Sec. 2.4 Cartesian metric, h33 = 1 in 2D); the basis is already global.
 template <int DIM, class Real>
-__global__ __launch_bounds__(BLOCK) void k_push_cart(StepArgs<Real> A) {
+__device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s, int32_t c,
+                                                 OffT<Real> q[3], Real u[3], Real w,
+                                                 const DepTarget<Real> &tg, const int shift[3]) {
   using PS = Pos<Real>;
-  int s;
-  int64_t local;
-  if (!locate(A.sp, s, local)) return;
-  const int64_t p = A.sp.off[s] + local;
   const GridConst &g = A.g;
-  const int32_t c = A.p.cell[p];
-  OffT<Real> q[3];
-  Real d[3];
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    q[a] = A.p.offs[a][p];
-    d[a] = (Real)PS::weight(q[a]);
-  }
-  if (A.write_prev) {
-    A.prev_cell[p] = c;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) A.prev_offs[a][p] = q[a];
-  }
-  if (c & DEAD_BIT) return;
   int i[3];
   cell_decode(g, c, i);
-
   Stencil1<Real> st[3];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], d[a]);
+  for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], (Real)PS::weight(q[a]));
   Real F[6];
   interp6<DIM, Real>(A.EB, g, st, F);
-
   Real E[3], B[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -46,52 +135,46 @@ __global__ __launch_bounds__(BLOCK) void k_push_cart(StepArgs<Real> A) {
     E[a] = F[a] * sc;
     B[a] = F[3 + a] * sc;
   }
-  Real u[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
-  const Real k = (Real)A.sp.k[s];
-  boris(k, E, B, u);
-
+  boris((Real)A.sp.k[s], E, B, u);
   // move (steps 6-7): offsets advance by dt u / (gamma Delta)
   const Real gi = rsqrt_r((Real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const Real dtr = (Real)A.dt;
   int m[3] = {0, 0, 0};
-  OffT<Real> qn[3];
   double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
   int inew[3] = {i[0], i[1], i[2]};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const Real dx = dtr * u[a] * gi / (Real)g.dx[a];
-    m[a] = PS::move(q[a], (double)dx, qn[a]);
+    OffT<Real> qn;
+    m[a] = PS::move(q[a], (double)dx, qn);
     za[a] = PS::exact(q[a]);
-    zb[a] = PS::exact(qn[a]) + (double)m[a];
+    zb[a] = PS::exact(qn) + (double)m[a];
+    q[a] = qn;
     int v = i[a] + m[a];
     v = (v < 0) ? v + g.n[a] : ((v >= g.n[a]) ? v - g.n[a] : v);  // periodic wrap
     inew[a] = v;
   }
   const Real dx3 = (DIM == 2) ? dtr * u[2] * gi : (Real)0;
-
-  // deposit (step 8) with the unwrapped step m; ghosts are folded afterwards
+  // deposit (step 8) with the unwrapped step m; periodic ghosts are folded
+  // later, a tile uses the image of the cell that keeps the box compact
   ZigZag<Real> z;
   zigzag<DIM, Real>(za, m, zb, z);
-  const Real C = (Real)A.sp.qdt[s] * A.p.w[p];
-  deposit<DIM, Real>(A.J, g, C, i, m, z, dx3);
-
-  A.p.cell[p] = cell_encode(g, inew);
+  int ib[3] = {i[0], i[1], i[2]};
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) A.p.offs[a][p] = qn[a];
-  A.p.u[0][p] = u[0];
-  A.p.u[1][p] = u[1];
-  A.p.u[2][p] = u[2];
+  for (int a = 0; a < DIM; ++a)
+    if (shift[a] && i[a] < (g.n[a] >> 1)) ib[a] += g.n[a];
+  deposit<DIM, Real>(tg, (Real)A.sp.qdt[s] * w, ib, m, z, dx3);
+  return cell_encode(g, inew);
 }
 
-// ---------------------------------------------------------------- axisymmetric grids
-// Tetrad (F^i_hat = sqrt(h_ii) F^i at x_p) and rotation of (r, theta, phi)_hat
-// into (x, y, z)_hat (Sec. 2.3 step 4), Boris in the global basis, then the
-// offset-relative move.  Metric and move run in CT (FP64 near the axis and
-// r_min when Real is float).
+// Axisymmetric: tetrad (F^i_hat = sqrt(h_ii) F^i at x_p) and rotation of
+// (r, theta, phi)_hat into (x, y, z)_hat (Sec. 2.3 step 4), Boris in the
+// global basis, offset-relative move.  Metric and move run in CT (FP64 near
+// the axis and r_min when Real is float).
 template <int GEOM, class CT, class Real, class D>
 __device__ __forceinline__ void axi_particle(const GridConst &g, Real k, double dt, int i1, int i2,
-                                             D d1, D d2, Real phi, const Real F[6],
-                                             Real u[3], CT &dx1, CT &dx2, CT &dphi) {
+                                             D d1, D d2, Real phi, const Real F[6], Real u[3],
+                                             CT &dx1, CT &dx2, CT &dphi) {
   const CT x1 = (CT)i1 + (CT)d1;
   const CT x2 = (CT)i2 + (CT)d2;
   const AxiMetric<CT> M = axi_metric<GEOM, CT>(g, x1, x2);
@@ -132,41 +215,28 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
 }
 
 template <int GEOM, class Real>
-__global__ __launch_bounds__(BLOCK) void k_push_axi(StepArgs<Real> A) {
+__device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int32_t c,
+                                            OffT<Real> q[3], Real u[3], Real w, Real &phi,
+                                            const DepTarget<Real> &tg) {
   using PS = Pos<Real>;
-  int s;
-  int64_t local;
-  if (!locate(A.sp, s, local)) return;
-  const int64_t p = A.sp.off[s] + local;
   const GridConst &g = A.g;
-  const int32_t c = A.p.cell[p];
-  const OffT<Real> q1 = A.p.offs[0][p], q2 = A.p.offs[1][p];
-  if (A.write_prev) {
-    A.prev_cell[p] = c;
-    A.prev_offs[0][p] = q1;
-    A.prev_offs[1][p] = q2;
-  }
-  if (c & DEAD_BIT) return;
-  const Real d1 = (Real)PS::weight(q1), d2 = (Real)PS::weight(q2);
   int i[3];
   cell_decode(g, c, i);
+  const Real d1 = (Real)PS::weight(q[0]), d2 = (Real)PS::weight(q[1]);
   Stencil1<Real> st[3];
   st[0] = stencil1(i[0], d1);
   st[1] = stencil1(i[1], d2);
   Real F[6];
   interp6<2, Real>(A.EB, g, st, F);
-  Real u[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
-  const Real phi = A.p.phi[p];
   const Real k = (Real)A.sp.k[s];
-
   double dx1, dx2;
   Real phinew, dx3;
   const bool near = (i[0] < g.fp64_cells) || (i[1] < g.fp64_cells) ||
                     (i[1] >= g.n[1] - g.fp64_cells);
   if (sizeof(Real) == 8 || near) {
     double dphi;
-    axi_particle<GEOM, double, Real>(g, k, A.dt, i[0], i[1], PS::exact(q1), PS::exact(q2), phi, F,
-                                     u, dx1, dx2, dphi);
+    axi_particle<GEOM, double, Real>(g, k, A.dt, i[0], i[1], PS::exact(q[0]), PS::exact(q[1]),
+                                     phi, F, u, dx1, dx2, dphi);
     phinew = next_phi<Real, double>(phi, dphi);
     dx3 = (Real)dphi;
   } else {
@@ -179,8 +249,8 @@ __global__ __launch_bounds__(BLOCK) void k_push_axi(StepArgs<Real> A) {
   }
   int m[3] = {0, 0, 0};
   OffT<Real> qn1, qn2;
-  m[0] = PS::move(q1, dx1, qn1);
-  m[1] = PS::move(q2, dx2, qn2);
+  m[0] = PS::move(q[0], dx1, qn1);
+  m[1] = PS::move(q[1], dx2, qn2);
   int inew[3] = {i[0] + m[0], i[1] + m[1], 0};
   // theta stays in [0, pi]: clamp rounding excursions
   if (inew[1] < 0) {
@@ -192,21 +262,185 @@ __global__ __launch_bounds__(BLOCK) void k_push_axi(StepArgs<Real> A) {
   }
   m[1] = inew[1] - i[1];
   const bool alive = inew[0] >= 0 && inew[0] < g.n[0];  // radial exit
-
-  const double za[3] = {PS::exact(q1), PS::exact(q2), 0.0};
+  const double za[3] = {PS::exact(q[0]), PS::exact(q[1]), 0.0};
   const double zb[3] = {PS::exact(qn1) + (double)m[0], PS::exact(qn2) + (double)m[1], 0.0};
   ZigZag<Real> z;
   zigzag<2, Real>(za, m, zb, z);
-  const Real C = (Real)A.sp.qdt[s] * A.p.w[p];
-  deposit<2, Real>(A.J, g, C, i, m, z, dx3);
+  deposit<2, Real>(tg, (Real)A.sp.qdt[s] * w, i, m, z, dx3);
+  q[0] = qn1;
+  q[1] = qn2;
+  phi = phinew;
+  return cell_encode(g, inew) | (alive ? 0 : DEAD_BIT);
+}
 
-  A.p.cell[p] = cell_encode(g, inew) | (alive ? 0 : DEAD_BIT);
-  A.p.offs[0][p] = qn1;
-  A.p.offs[1][p] = qn2;
-  A.p.phi[p] = phinew;
-  A.p.u[0][p] = u[0];
-  A.p.u[1][p] = u[1];
-  A.p.u[2][p] = u[2];
+// the block's particles one after the other (each thread: up to PPT)
+template <int GEOM, int DIM, class Real>
+__device__ __forceinline__ void push_particles(const StepArgs<Real> &A, int s, int cnt,
+                                               int32_t cl[PPT], OffT<Real> qd[3][PPT],
+                                               Real uu[3][PPT], const Real ww[PPT], Real ph[PPT],
+                                               const DepTarget<Real> &tg, const int shift[3]) {
+  for (int r = 0; r < PPT; ++r) {
+    if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
+    OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
+                       DIM > 2 ? qd[2][r] : (OffT<Real>)0};
+    Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
+    if (GEOM == 0) {
+      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tg, shift);
+    } else {
+      Real p = ph[r];
+      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tg);
+      ph[r] = p;
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
+  }
+}
+
+// ---------------------------------------------------------------- the kernel
+template <int GEOM, int DIM, class Real>
+__global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
+  constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Real);
+  __shared__ Real tile[TILE_VALS];
+  __shared__ int red[6 * (BLOCK / 64)];
+  const GridConst &g = A.g;
+  int s;
+  int64_t c0;
+  if (!locate_chunk(A.sp, s, c0)) return;  // uniform over the block
+  const int64_t first = c0 + (int64_t)threadIdx.x * PPT;
+  const int cnt = (int)max((int64_t)0, min((int64_t)PPT, A.sp.n[s] - first));
+  const int64_t p0 = A.sp.off[s] + first;
+
+  int32_t cl[PPT];
+  OffT<Real> qd[3][PPT];
+  load_n(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) load_n(A.p.offs[a] + p0, cnt, qd[a], (OffT<Real>)0);
+  if (A.write_prev) {
+    store_n(A.prev_cell + p0, cnt, cl);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) store_n(A.prev_offs[a] + p0, cnt, qd[a]);
+  }
+
+  // bounding box of the chunk's current cells; a periodic dimension whose
+  // cells span more than half the box is unwrapped (cells below N/2 shifted
+  // by +N) so that a chunk straddling the boundary stays compact
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  int ic[PPT][3];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    cell_decode(g, cl[r], ic[r]);
+    if (cl[r] & DEAD_BIT) continue;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], ic[r][d]);
+      hi[d] = max(hi[d], ic[r][d]);
+    }
+  }
+  block_minmax3(lo, hi, red);
+  if (lo[0] > hi[0]) return;  // no live particle in the chunk (uniform)
+  int shift[3] = {0, 0, 0};
+  if (GEOM == 0) {
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      shift[d] = (hi[d] - lo[d] > (g.n[d] >> 1)) ? 1 : 0;
+      any = any || shift[d];
+    }
+    if (any) {  // uniform: recompute the box on the shifted cells
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = INT32_MAX;
+        hi[d] = INT32_MIN;
+      }
+#pragma unroll
+      for (int r = 0; r < PPT; ++r) {
+        if (cl[r] & DEAD_BIT) continue;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int v = ic[r][d] + ((shift[d] && ic[r][d] < (g.n[d] >> 1)) ? g.n[d] : 0);
+          lo[d] = min(lo[d], v);
+          hi[d] = max(hi[d], v);
+        }
+      }
+      block_minmax3(lo, hi, red);
+    }
+  }
+  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    t0[d] = lo[d] - 1;  // stencils reach cell - 1 ... cell + 2
+    ts[d] = hi[d] - lo[d] + 4;
+  }
+  const int64_t T = (int64_t)ts[0] * ts[1] * ts[2];
+  const bool use_tile = 3 * T <= TILE_VALS;
+  if (A.stats && threadIdx.x == 0) {
+    atomicAdd(A.stats, 1);
+    if (!use_tile) atomicAdd(A.stats + 1, 1);
+  }
+
+  Real uu[3][PPT], ww[PPT], ph[PPT];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
+  load_n(A.p.w + p0, cnt, ww, (Real)0);
+  if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
+
+  if (use_tile) {
+    for (int64_t x = threadIdx.x; x < 3 * T; x += BLOCK) tile[x] = (Real)0;
+    __syncthreads();
+    DepTarget<Real> tg;
+    tg.J = tile;
+    tg.cs = T;
+    tg.sy = ts[0];
+    tg.sz = (int64_t)ts[0] * ts[1];
+    tg.o[0] = t0[0];
+    tg.o[1] = t0[1];
+    tg.o[2] = t0[2];
+    push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tg, shift);
+  } else {
+    DepTarget<Real> tg;
+    tg.J = A.J;
+    tg.cs = g.npts;
+    tg.sy = g.np[0];
+    tg.sz = (int64_t)g.np[0] * g.np[1];
+    tg.o[0] = -NG;
+    tg.o[1] = -NG;
+    tg.o[2] = (DIM == 3) ? -NG : 0;
+    const int noshift[3] = {0, 0, 0};
+    push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tg, noshift);
+  }
+
+  store_n(A.p.cell + p0, cnt, cl);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
+  if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+
+  if (use_tile) {
+    __syncthreads();
+    const int64_t np0 = g.np[0], np01 = np0 * g.np[1];
+    for (int64_t x = threadIdx.x; x < 3 * T; x += BLOCK) {
+      const Real v = tile[x];
+      if (v == (Real)0) continue;
+      const int64_t comp = x / T;
+      int64_t rem = x - comp * T;
+      const int ix = (int)(rem % ts[0]);
+      rem /= ts[0];
+      const int iy = (int)(rem % ts[1]);
+      const int iz = (int)(rem / ts[1]);
+      int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
+      if (GEOM == 0) {  // periodic: add straight into the image in the active region
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) gi[d] = (gi[d] + 2 * g.n[d]) % g.n[d];
+      }
+      const int64_t gidx = comp * g.npts + (int64_t)(gi[0] + NG) + np0 * (int64_t)(gi[1] + NG) +
+                           ((DIM == 3) ? np01 * (int64_t)(gi[2] + NG) : 0);
+      atomic_add_r(A.J + gidx, v);
+    }
+  }
 }
 
 template <class Real>
@@ -216,13 +450,13 @@ hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s) {
   dim3 grid((unsigned)nblk), block(BLOCK);
   if (a.g.geom == 0) {
     if (a.g.dim == 2)
-      hipLaunchKernelGGL((k_push_cart<2, Real>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_push<0, 2, Real>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((k_push_cart<3, Real>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_push<0, 3, Real>), grid, block, 0, s, a);
   } else if (a.g.geom == 1) {
-    hipLaunchKernelGGL((k_push_axi<1, Real>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_push<1, 2, Real>), grid, block, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_push_axi<2, Real>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_push<2, 2, Real>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }

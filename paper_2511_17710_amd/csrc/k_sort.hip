@@ -1,8 +1,8 @@
 // k_sort.hip -- stable per-cell counting sort of a particle species.
 //
-// Least-significant-digit radix sort on the packed cell key (8-bit digits,
-// dead particles carry the largest key), so equal keys keep their previous
-// order and the permutation is unique.  Per pass: tile histograms (digit-major
+// Least-significant-digit radix sort on a cell key that orders cells brick by
+// brick (8-bit digits, dead particles carry the largest key), so equal keys
+// keep their previous order and the permutation is unique.  Per pass: tile histograms (digit-major
 // matrix), one exclusive scan of that matrix, and a stable in-tile ranking by
 // eight one-bit splits in LDS followed by a scatter.  A gather then reorders
 // every SoA array into the second particle set.
@@ -38,15 +38,28 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh_w
   return pre + x - v;
 }
 
-// keys of one species range: packed cell, or 1 << (keybits - 1) when dead
-__global__ __launch_bounds__(SORT_THREADS) void k_make_keys(const int32_t *__restrict__ cell,
+// keys of one species range: cells brick by brick (brick index, then the cell
+// inside the brick, x fastest in both), or 1 << (keybits - 1) when dead
+__global__ __launch_bounds__(SORT_THREADS) void k_make_keys(GridConst g,
+                                                            const int32_t *__restrict__ cell,
                                                             int64_t n, uint32_t deadkey,
                                                             uint32_t *__restrict__ keys,
                                                             int32_t *__restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
   if (i >= n) return;
   const int32_t c = cell[i];
-  keys[i] = (c & DEAD_BIT) ? deadkey : (uint32_t)c;
+  uint32_t key = deadkey;
+  if (!(c & DEAD_BIT)) {
+    const int ii[3] = {(c & g.mask1) - 1, (c >> g.shift2) & g.mask2, (c >> g.shift3) & g.mask3};
+    const uint32_t bi[3] = {(uint32_t)(ii[0] / g.brick[0]), (uint32_t)(ii[1] / g.brick[1]),
+                            (uint32_t)(ii[2] / g.brick[2])};
+    const uint32_t li[3] = {(uint32_t)(ii[0] % g.brick[0]), (uint32_t)(ii[1] % g.brick[1]),
+                            (uint32_t)(ii[2] % g.brick[2])};
+    const uint32_t brick = bi[0] + (uint32_t)g.nbrick[0] * (bi[1] + (uint32_t)g.nbrick[1] * bi[2]);
+    const uint32_t local = li[0] + (uint32_t)g.brick[0] * (li[1] + (uint32_t)g.brick[1] * li[2]);
+    key = brick * (uint32_t)(g.brick[0] * g.brick[1] * g.brick[2]) + local;
+  }
+  keys[i] = key;
   vals[i] = (int32_t)i;
 }
 
@@ -206,7 +219,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
                                const SortScratch &S, int32_t *perm_out, int keybits,
                                hipStream_t s) {
-  (void)g;
   if (n <= 0) return hipSuccess;
   const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   if (ntiles > S.max_tiles) return hipErrorInvalidValue;
@@ -215,7 +227,7 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
   if (nchunks > SCAN_CHUNK) return hipErrorInvalidValue;
   const uint32_t deadkey = 1u << (keybits - 1);
   hipLaunchKernelGGL(k_make_keys, dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)),
-                     dim3(SORT_THREADS), 0, s, cell, n, deadkey, S.keys[0], S.vals[0]);
+                     dim3(SORT_THREADS), 0, s, g, cell, n, deadkey, S.keys[0], S.vals[0]);
   const int passes = (keybits + 7) / 8;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;

@@ -42,7 +42,8 @@ struct pic_ctx {
   uint64_t set_bytes = 0;
   uint64_t p_cell = 0, p_offs[3]{NONE, NONE, NONE}, prev_bytes = 0;
   // scratch layout
-  uint64_t s_keys[2]{}, s_vals[2]{}, s_hist = 0, s_bsum = 0, s_perm = 0, scratch_bytes = 0;
+  uint64_t s_keys[2]{}, s_vals[2]{}, s_hist = 0, s_bsum = 0, s_perm = 0, s_stats = 0,
+           scratch_bytes = 0;
   int64_t max_tiles = 0;
   int keybits = 0;
   uint64_t ckpt_bytes = 0;
@@ -54,7 +55,19 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   int64_t step = 0;
   double dx_min = 0;  // Sec. 2.4 CFL length
+  bool timing = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int kind;  // 0 push, 1 sort, 2 adjoint
+  };
+  std::vector<Ev> events;
   std::string err;
+  ~pic_ctx() {
+    for (auto &e : events) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+  }
 };
 
 namespace {
@@ -121,14 +134,14 @@ PSet<Real> pset_of(const pic_ctx *c, int which) {
   return p;
 }
 
-SpeciesTable species_table(const pic_ctx *c, double dt) {
+SpeciesTable species_table(const pic_ctx *c, double dt, int64_t per_block) {
   SpeciesTable t{};
   t.nspec = c->nspec;
   t.blk0[0] = 0;
   for (int s = 0; s < c->nspec; ++s) {
     t.off[s] = (int64_t)c->off[s];
     t.n[s] = (int64_t)c->cnt[s];
-    t.blk0[s + 1] = t.blk0[s] + (t.n[s] + BLOCK - 1) / BLOCK;
+    t.blk0[s + 1] = t.blk0[s] + (t.n[s] + per_block - 1) / per_block;
     t.k[s] = c->q[s] * dt / (2.0 * c->m[s] * c->d.rho0);
     t.qdt[s] = c->q[s] / dt;
   }
@@ -136,8 +149,27 @@ SpeciesTable species_table(const pic_ctx *c, double dt) {
   return t;
 }
 
+// records the start event of a timed region; returns its index or -1
+int ev_begin(pic_ctx *c, int kind) {
+  if (!c->timing) return -1;
+  pic_ctx::Ev e{};
+  if (hipEventCreate(&e.a) != hipSuccess) return -1;
+  if (hipEventCreate(&e.b) != hipSuccess) {
+    (void)hipEventDestroy(e.a);
+    return -1;
+  }
+  e.kind = kind;
+  (void)hipEventRecord(e.a, c->stream);
+  c->events.push_back(e);
+  return (int)c->events.size() - 1;
+}
+void ev_end(pic_ctx *c, int idx) {
+  if (idx >= 0) (void)hipEventRecord(c->events[idx].b, c->stream);
+}
+
 template <class Real>
 pic_status do_sort(pic_ctx *c) {
+  const int ev = ev_begin(c, 1);
   SortScratch S{};
   for (int a = 0; a < 2; ++a) {
     S.keys[a] = reinterpret_cast<uint32_t *>(c->scratch + c->s_keys[a]);
@@ -159,6 +191,7 @@ pic_status do_sort(pic_ctx *c) {
   }
   // species with no particles keep nothing worth copying; flip the set
   c->active ^= 1;
+  ev_end(c, ev);
   return PIC_OK;
 }
 
@@ -166,7 +199,7 @@ template <class Real>
 pic_status do_step(pic_ctx *c, double dt, bool write_prev) {
   StepArgs<Real> a{};
   a.g = c->g;
-  a.sp = species_table(c, dt);
+  a.sp = species_table(c, dt, PUSH_CHUNK);
   a.p = pset_of<Real>(c, c->active);
   a.prev_cell = reinterpret_cast<int32_t *>(c->prev + c->p_cell);
   for (int d = 0; d < 3; ++d)
@@ -175,9 +208,12 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev) {
   a.J = reinterpret_cast<Real *>(c->current);
   a.dt = dt;
   a.write_prev = write_prev ? 1 : 0;
+  a.stats = c->timing ? reinterpret_cast<int32_t *>(c->scratch + c->s_stats) : nullptr;
   hipError_t e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "zero J");
+  const int ev = ev_begin(c, 0);
   e = launch_push_deposit<Real>(a, c->stream);
+  ev_end(c, ev);
   if (e != hipSuccess) return hipchk(c, e, "push_deposit");
   e = launch_fold_ghosts<Real>(c->g, a.J, 3, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "fold J");
@@ -291,7 +327,18 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   g.mask1 = (1 << b1) - 1;
   g.mask2 = (1 << b2) - 1;
   g.mask3 = (1 << b3) - 1;
-  c->keybits = b1 + b2 + b3 + 1;
+  // sort order: 4x4x4 bricks in 3D, 8x8 in 2D
+  for (int a = 0; a < 3; ++a) {
+    g.brick[a] = a < d.dim ? (d.dim == 3 ? 4 : 8) : 1;
+    g.nbrick[a] = (g.n[a] + g.brick[a] - 1) / g.brick[a];
+  }
+  const int64_t nkeys = (int64_t)g.nbrick[0] * g.nbrick[1] * g.nbrick[2] *
+                        g.brick[0] * g.brick[1] * g.brick[2];
+  if (bits_for(nkeys) > 30) {
+    delete c;
+    return PIC_E_UNSUPPORTED;
+  }
+  c->keybits = bits_for(nkeys) + 1;
   c->eb = d.prec == PIC_F64 ? 8 : 4;
   // capacity: room for per-species alignment to 64 elements
   c->capacity = align_up(d.max_particles, 64) + 64 * MAXSP;
@@ -337,6 +384,8 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   o += align_up((uint64_t)SCAN_CHUNK * 4, ALIGN);
   c->s_perm = o;
   o += ai;
+  c->s_stats = o;
+  o += ALIGN;
   c->scratch_bytes = o;
   // checkpoint: cell, offsets, u, phi
   c->ckpt_bytes = ai + (uint64_t)d.dim * ab + 3 * ab + (d.geom != PIC_CART ? ab : 0);
@@ -694,6 +743,46 @@ pic_status pic_step_count(const pic_ctx *c, int64_t *step) {
   if (!c || !step) return PIC_E_ARG;
   *step = c->step;
   return PIC_OK;
+}
+
+pic_status pic_timing_enable(pic_ctx *c, int32_t enable) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "timing before bind_buffers");
+  c->timing = enable != 0;
+  return hipchk(c, hipMemsetAsync(c->scratch + c->s_stats, 0, 16, c->stream), "timing_enable");
+}
+
+pic_status pic_timing_read(pic_ctx *c, pic_timing *out) {
+  if (!c || !out) return PIC_E_ARG;
+  std::memset(out, 0, sizeof *out);
+  hipError_t err = hipSuccess;
+  for (auto &e : c->events) {
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventSynchronize(e.b);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e.a, e.b);
+    if (e.kind == 0) {
+      out->push_launches += 1;
+      out->push_ms += ms;
+    } else if (e.kind == 1) {
+      out->sort_calls += 1;
+      out->sort_ms += ms;
+    } else {
+      out->adjoint_launches += 1;
+      out->adjoint_ms += ms;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->events.clear();
+  if (err == hipSuccess && c->bound) {
+    int32_t st[4] = {0, 0, 0, 0};
+    err = hipMemcpyAsync(st, c->scratch + c->s_stats, 16, hipMemcpyDeviceToHost, c->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+    out->push_blocks = st[0];
+    out->push_fallback_blocks = st[1];
+    if (err == hipSuccess) err = hipMemsetAsync(c->scratch + c->s_stats, 0, 16, c->stream);
+  }
+  return hipchk(c, err, "timing_read");
 }
 
 pic_status pic_adjoint_workspace(const pic_ctx *c, int32_t K, int32_t m, uint64_t *bytes) {

@@ -231,36 +231,43 @@ __device__ __forceinline__ void zigzag(const double a[3], const int m[3], const 
 __device__ __forceinline__ void atomic_add_r(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_r(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// Scatter of the two segments into J (padded layout; indices may reach the
-// ghost layer, periodic ghosts are folded after the step).
+// Where a deposit lands: the global current (padded layout) or a block's LDS
+// tile; element (I, J, K) of component c sits at
+// c*cs + (I - o0) + sy*(J - o1) + sz*(K - o2).
+template <class Real>
+struct DepTarget {
+  Real *J;
+  int64_t cs, sy, sz;
+  int o[3];
+};
+
+// Scatter of the two zig-zag segments (indices may reach the ghost layer of
+// the global array; periodic ghosts are folded after the step).
 template <int DIM, class Real>
-__device__ __forceinline__ void deposit(Real *__restrict__ J, const GridConst &g, Real C,
-                                        const int i0[3], const int m[3], const ZigZag<Real> &z,
-                                        Real dx3) {
-  const int64_t npts = g.npts;
-  const int64_t np0 = g.np[0];
-  const int64_t np01 = np0 * g.np[1];
+__device__ __forceinline__ void deposit(const DepTarget<Real> &t, Real C, const int i0[3],
+                                        const int m[3], const ZigZag<Real> &z, Real dx3) {
+  const int64_t cs = t.cs, sy = t.sy, sz = t.sz;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int I = i0[0] + (s ? m[0] : 0);
-    const int Jc = i0[1] + (s ? m[1] : 0);
-    const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) : 0;
-    const int64_t base = pad_index(g, I, Jc, K, DIM);
+    const int I = i0[0] + (s ? m[0] : 0) - t.o[0];
+    const int Jc = i0[1] + (s ? m[1] : 0) - t.o[1];
+    const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) - t.o[2] : 0;
+    const int64_t base = (int64_t)I + sy * (int64_t)Jc + sz * (int64_t)K;
     const Real Fx = z.F[s][0], Fy = z.F[s][1];
     const Real Wx = z.W[s][0], Wy = z.W[s][1];
     if (DIM == 2) {
       const Real cx = C * Fx, cy = C * Fy;
-      atomic_add_r(J + base, cx * ((Real)1 - Wy));
-      atomic_add_r(J + base + np0, cx * Wy);
-      atomic_add_r(J + npts + base, cy * ((Real)1 - Wx));
-      atomic_add_r(J + npts + base + 1, cy * Wx);
+      atomic_add_r(t.J + base, cx * ((Real)1 - Wy));
+      atomic_add_r(t.J + base + sy, cx * Wy);
+      atomic_add_r(t.J + cs + base, cy * ((Real)1 - Wx));
+      atomic_add_r(t.J + cs + base + 1, cy * Wx);
       const Real h = C * dx3 * (Real)0.5;
       const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
-      Real *J3 = J + 2 * npts + base;
+      Real *J3 = t.J + 2 * cs + base;
       atomic_add_r(J3, h * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy));
       atomic_add_r(J3 + 1, h * (Wx * ((Real)1 - Wy) - cxy));
-      atomic_add_r(J3 + np0, h * (((Real)1 - Wx) * Wy - cxy));
-      atomic_add_r(J3 + np0 + 1, h * (Wx * Wy + cxy));
+      atomic_add_r(J3 + sy, h * (((Real)1 - Wx) * Wy - cxy));
+      atomic_add_r(J3 + sy + 1, h * (Wx * Wy + cxy));
     } else {
       const Real Fz = z.F[s][2], Wz = z.W[s][2];
       const Real cx = C * Fx, cy = C * Fy, cz = C * Fz;
@@ -268,21 +275,21 @@ __device__ __forceinline__ void deposit(Real *__restrict__ J, const GridConst &g
       const Real cxz = Fx * Fz * (Real)(1.0 / 12.0);
       const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
       const Real gx = (Real)1 - Wx, gy = (Real)1 - Wy, gz = (Real)1 - Wz;
-      Real *J1 = J + base;
+      Real *J1 = t.J + base;
       atomic_add_r(J1, cx * (gy * gz + cyz));
-      atomic_add_r(J1 + np0, cx * (Wy * gz - cyz));
-      atomic_add_r(J1 + np01, cx * (gy * Wz - cyz));
-      atomic_add_r(J1 + np01 + np0, cx * (Wy * Wz + cyz));
-      Real *J2 = J + npts + base;
+      atomic_add_r(J1 + sy, cx * (Wy * gz - cyz));
+      atomic_add_r(J1 + sz, cx * (gy * Wz - cyz));
+      atomic_add_r(J1 + sz + sy, cx * (Wy * Wz + cyz));
+      Real *J2 = t.J + cs + base;
       atomic_add_r(J2, cy * (gx * gz + cxz));
       atomic_add_r(J2 + 1, cy * (Wx * gz - cxz));
-      atomic_add_r(J2 + np01, cy * (gx * Wz - cxz));
-      atomic_add_r(J2 + np01 + 1, cy * (Wx * Wz + cxz));
-      Real *J3 = J + 2 * npts + base;
+      atomic_add_r(J2 + sz, cy * (gx * Wz - cxz));
+      atomic_add_r(J2 + sz + 1, cy * (Wx * Wz + cxz));
+      Real *J3 = t.J + 2 * cs + base;
       atomic_add_r(J3, cz * (gx * gy + cxy));
       atomic_add_r(J3 + 1, cz * (Wx * gy - cxy));
-      atomic_add_r(J3 + np0, cz * (gx * Wy - cxy));
-      atomic_add_r(J3 + np0 + 1, cz * (Wx * Wy + cxy));
+      atomic_add_r(J3 + sy, cz * (gx * Wy - cxy));
+      atomic_add_r(J3 + sy + 1, cz * (Wx * Wy + cxy));
     }
   }
 }

@@ -50,6 +50,12 @@ class Layout(C.Structure):
                 ("prev_cell", C.c_uint64), ("prev_offs", C.c_uint64 * 3)]
 
 
+class Timing(C.Structure):
+    _fields_ = [("push_launches", C.c_int64), ("push_ms", C.c_double), ("sort_calls", C.c_int64),
+                ("sort_ms", C.c_double), ("adjoint_launches", C.c_int64), ("adjoint_ms", C.c_double),
+                ("push_blocks", C.c_int64), ("push_fallback_blocks", C.c_int64)]
+
+
 class ParticleView(C.Structure):
     _fields_ = [("n", C.c_uint64), ("cell", C.POINTER(C.c_int32)), ("offs", C.POINTER(C.c_double)),
                 ("u", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
@@ -92,6 +98,8 @@ def lib():
             "pic_forward_checkpointed": [vp, dbl, i32, i32, vp],
             "pic_backward": [vp, dbl, i32, i32, vp, vp, vp, vp, vp],
             "pic_last_error": [vp],
+            "pic_timing_enable": [vp, i32],
+            "pic_timing_read": [vp, C.POINTER(Timing)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -242,6 +250,14 @@ class Context:
         v = C.c_int64()
         self._check(lib().pic_step_count(self.h, C.byref(v)), "step_count")
         return v.value
+
+    def timing_enable(self, on=True):
+        self._check(lib().pic_timing_enable(self.h, 1 if on else 0), "timing_enable")
+
+    def timing_read(self):
+        t = Timing()
+        self._check(lib().pic_timing_read(self.h, C.byref(t)), "timing_read")
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
 
     # -------------------------------------------------------------- views / readback
     def _view(self, buf, byte_off, count, dtype):

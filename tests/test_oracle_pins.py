@@ -479,21 +479,44 @@ def test_sort_matches_numpy_stable_argsort():
 
 
 def test_run_sorts_by_cell_and_dead_last():
+    """Stable sort by cell in brick order (8x8 bricks in 2D, x fastest between
+    and inside bricks), dead particles last; checked against numpy's stable
+    argsort of the key written out here."""
     rng = np.random.default_rng(15)
-    n = (6, 5, 1)
+    n = (20, 12, 1)
     g = O.make_grid("cart", 2, n, (0, 0, 0), n)
-    P = 500
-    cell = np.stack([rng.integers(0, 6, P), rng.integers(0, 5, P), np.zeros(P)], 1).astype(np.int32)
+    P = 3000
+    cell = np.stack([rng.integers(0, 20, P), rng.integers(0, 12, P), np.zeros(P)], 1).astype(np.int32)
     offs = np.concatenate([rng.random((P, 2)), np.zeros((P, 1))], 1)
     alive = (rng.random(P) > 0.2).astype(np.int32)
     sp = [dict(q=1.0, m=1.0, cell=cell, offs=offs, u=np.zeros((P, 3)), w=np.arange(P, dtype=float),
                phi=None, alive=alive)]
     EB = np.zeros((6,) + O.padded_shape(g))
     out, _ = O.run(g, 0.1, 1, EB, sp, sort_every=1)
-    key = np.where(alive == 1, cell[:, 0] + 6 * cell[:, 1], np.iinfo(np.int32).max)
+    nbx = 3  # ceil(20 / 8)
+    brick = cell[:, 0] // 8 + nbx * (cell[:, 1] // 8)
+    local = cell[:, 0] % 8 + 8 * (cell[:, 1] % 8)
+    key = np.where(alive == 1, brick * 64 + local, np.iinfo(np.int32).max)
     perm = np.argsort(key, kind="stable")
     np.testing.assert_array_equal(out[0]["perm"], perm)
     np.testing.assert_array_equal(out[0]["w"], np.arange(P, dtype=float)[perm])
+
+
+def test_sort_brick_order_3d():
+    """3D: 4x4x4 bricks."""
+    rng = np.random.default_rng(18)
+    n = (9, 8, 6)
+    g = O.make_grid("cart", 3, n, (0, 0, 0), n)
+    P = 4000
+    cell = np.stack([rng.integers(0, n[d], P) for d in range(3)], 1).astype(np.int32)
+    sp = [dict(q=1.0, m=1.0, cell=cell, offs=rng.random((P, 3)), u=np.zeros((P, 3)),
+               w=np.ones(P), phi=None, alive=np.ones(P, np.int32))]
+    out, _ = O.run(g, 0.1, 1, np.zeros((6,) + O.padded_shape(g)), sp, sort_every=1)
+    nb = [3, 2, 2]
+    b = cell // 4
+    lc = cell % 4
+    key = (b[:, 0] + nb[0] * (b[:, 1] + nb[1] * b[:, 2])) * 64 + lc[:, 0] + 4 * (lc[:, 1] + 4 * lc[:, 2])
+    np.testing.assert_array_equal(out[0]["perm"], np.argsort(key, kind="stable"))
 
 
 # --------------------------------------------------------------------------- adjoint
