@@ -71,6 +71,44 @@ def run_gpu(wl, prec, steps, warmup, log):
     return res
 
 
+def run_adjoint(prec, log, name="cart3d_64_adj"):
+    """Checkpointed forward (K steps, state every m) and the hand-written
+    reverse sweep of L = sum(W * J_K) on the 3D Cartesian 64^3 workload."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    from paper_2511_17710_amd import workloads as W
+    wl = W.by_name(name)
+    K, m = wl.K, wl.ckpt_every
+    ctx = P.from_workload(wl, prec=prec, sort_every=0)
+    ctx.sort()  # cell order before the differentiated steps (not part of the map)
+    dt = ctx.timestep_from_cfl(wl.cfl)
+    lamJ = torch.from_numpy(wl.W).to(device="cuda", dtype=ctx.dtype)
+    ctx.forward_checkpointed(dt, 2, 1)  # warm-up
+    ctx.backward(dt, 2, 1, lamJ)
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    s = ctx.stream
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(s)
+    ctx.forward_checkpointed(dt, K, m)
+    e[1].record(s)
+    dEB, du0 = ctx.backward(dt, K, m, lamJ)
+    e[2].record(s)
+    torch.cuda.synchronize()
+    tm = ctx.timing_read()
+    n = wl.nparticles
+    res = dict(workload=wl.name, particles=n, K=K, checkpoint_every=m,
+               forward_ns_per_particle_step=e[0].elapsed_time(e[1]) * 1e6 / (n * K),
+               backward_ns_per_particle_step=e[1].elapsed_time(e[2]) * 1e6 / (n * K),
+               adjoint_kernel_ms_avg=tm["adjoint_ms"] / max(tm["adjoint_launches"], 1),
+               grad_norm=float(dEB.double().norm()))
+    log(f"[bench] adjoint {prec}: {res}")
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, sample_per_species, steps, log):
     """FP64 CPU reference (single thread) on the first particles of each species."""
     from oracle import oracle as O
@@ -103,6 +141,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -136,6 +175,9 @@ def main():
     r32 = run_gpu(wl, "f32", args.steps, args.warmup, log)
     r64 = None if args.skip_fp64 else run_gpu(wl, "f64", args.steps, args.warmup, log)
     cpu = None if args.skip_cpu else cpu_baseline(wl, args.cpu_sample, args.cpu_steps, log)
+    adj = None
+    if not args.skip_adjoint:
+        adj = {p: run_adjoint(p, log) for p in (("f32",) if args.skip_fp64 else ("f32", "f64"))}
 
     n = wl.nparticles
     bpp32 = algorithmic_bytes_per_particle(wl.dim, "f32", ncells, n, has_phi)
@@ -169,6 +211,8 @@ def main():
         r64["achieved_GBs"] = round(bpp64 * n / (r64["push_ms_avg"] * 1e-3) / 1e9, 1)
         out["fp64"] = r64
         out["fp32_vs_fp64_speedup"] = round(r64["ns_per_particle_step"] / r32["ns_per_particle_step"], 3)
+    if adj:
+        out["adjoint"] = adj
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -73,6 +73,7 @@ struct StepArgs {
   Real *J;
   double dt;
   int write_prev;
+  int deposit;             // 0: move only (adjoint recompute)
   int32_t *stats;          // [0]: blocks, [1]: blocks that deposited with global atomics
 };
 

@@ -1,0 +1,313 @@
+// k_adjoint.hip -- reverse-mode derivative of one particle step (Cartesian
+// grids), written by hand: the forward step of the particle is recomputed in
+// registers from its stored state, then the adjoints are propagated backwards
+// through the zig-zag deposit (a gather of dL/dJ), the move, the Boris push
+// and the interpolation (a scatter into dL/dE, dL/dB).  Discrete branches
+// (cell crossings, the relay clamp, the half-cell stagger choice) take the
+// derivative of the branch the forward step took.
+#include "step_device.h"
+
+namespace picstep {
+
+// forward interpolation of one component that also returns the corner values
+template <int DIM, class Real>
+__device__ __forceinline__ void corners(const Real *__restrict__ A, const GridConst &g, int bx,
+                                        int by, int bz, Real c[8], int idx[8]) {
+  const int np0 = g.np[0], np01 = np0 * g.np[1];
+  const int base = pad_index(g, bx, by, bz, DIM);
+#pragma unroll
+  for (int e = 0; e < (1 << DIM); ++e) {
+    const int o = (e & 1) + ((e >> 1) & 1) * np0 + ((DIM == 3) ? ((e >> 2) & 1) * np01 : 0);
+    idx[e] = base + o;
+    c[e] = A[base + o];
+  }
+}
+
+template <int DIM, class Real>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
+  using PS = Pos<Real>;
+  int s;
+  int64_t local;
+  if (!locate(A.sp, s, local)) return;
+  const int64_t p = A.sp.off[s] + local;
+  const GridConst &g = A.g;
+  const int32_t cc = A.p.cell[p];
+  if (cc & DEAD_BIT) return;  // frozen particle: identity map, adjoints pass through
+  int i[3];
+  cell_decode(g, cc, i);
+  OffT<Real> q[3];
+  Real d[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    q[a] = A.p.offs[a][p];
+    d[a] = (Real)PS::weight(q[a]);
+  }
+  const Real u0[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
+  const Real w = A.p.w[p];
+  const Real k = (Real)A.sp.k[s];
+  const Real dtr = (Real)A.dt;
+
+  // ---------------- forward recompute (step 3: interpolation, keeping corners)
+  Stencil1<Real> st[3];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], d[a]);
+  Real F[6];
+  interp6<DIM, Real>(A.EB, g, st, F);
+  Real E[3], B[3], sc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sc[a] = (a < DIM) ? (Real)g.dx[a] : (Real)1;
+    E[a] = F[a] * sc[a];
+    B[a] = F[3 + a] * sc[a];
+  }
+  // step 5: Boris, keeping intermediates
+  Real um[3], t[3], s3[3], up[3], un[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) um[a] = u0[a] + k * E[a];
+  // same operations as the forward kernel, so the recomputed step is identical
+  const Real igm = rsqrt_r((Real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) t[a] = k * B[a] * igm;
+  const Real tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  const Real sf = (Real)2 * rcp_r((Real)1 + tt);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) s3[a] = t[a] * sf;
+  up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+  up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+  up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+  un[0] = um[0] + (up[1] * s3[2] - up[2] * s3[1]) + k * E[0];
+  un[1] = um[1] + (up[2] * s3[0] - up[0] * s3[2]) + k * E[1];
+  un[2] = um[2] + (up[0] * s3[1] - up[1] * s3[0]) + k * E[2];
+  // steps 6-7: move
+  const Real ig = rsqrt_r((Real)1 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+  int m[3] = {0, 0, 0};
+  double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const Real dx = dtr * un[a] * ig / (Real)g.dx[a];  // as in the forward kernel
+    OffT<Real> qn;
+    m[a] = PS::move(q[a], (double)dx, qn);
+    za[a] = PS::exact(q[a]);
+    zb[a] = PS::exact(qn) + (double)m[a];
+  }
+
+  // ---------------- reverse
+  Real ab[3] = {0, 0, 0};   // adjoint of the old offsets
+  Real dxb[3] = {0, 0, 0};  // adjoint of the in-plane displacements
+  Real dx3b = 0;            // adjoint of the out-of-plane displacement (2D)
+  // adjoint of the new offsets passes to the old offset and the displacement
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const Real l = A.lam_d[a][p];
+    ab[a] += l;
+    dxb[a] += l;
+  }
+  // step 8 reversed: gather dL/dJ through the zig-zag segments
+  if (A.lamJ) {
+    const Real C = (Real)A.sp.qdt[s] * w;
+    Real Fs[2][3] = {{0, 0, 0}, {0, 0, 0}}, Ws[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    bool mid_free[3] = {false, false, false};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double lo = (double)(min(0, m[a]) + 1), hi = (double)max(0, m[a]);
+      const double mid = (za[a] + zb[a]) * 0.5;
+      const double xr = fmin(lo, fmax(hi, mid));
+      mid_free[a] = (mid >= hi) && (mid <= lo);
+      Fs[0][a] = (Real)(xr - za[a]);
+      Fs[1][a] = (Real)(zb[a] - xr);
+      Ws[0][a] = (Real)((za[a] + xr) * 0.5);
+      Ws[1][a] = (Real)((xr + zb[a]) * 0.5 - (double)m[a]);
+    }
+    const Real dx3 = (DIM == 2) ? dtr * un[2] * ig : (Real)0;
+    Real Fb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Wb[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    const int cs = (int)g.npts, sy = g.np[0], sz = g.np[0] * g.np[1];
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      const int I = i[0] + (sg ? m[0] : 0), Jc = i[1] + (sg ? m[1] : 0);
+      const int K = (DIM == 3) ? i[2] + (sg ? m[2] : 0) : 0;
+      const int base = pad_index(g, I, Jc, K, DIM);
+      const Real *L = A.lamJ;
+      const Real Fx = Fs[sg][0], Fy = Fs[sg][1], Wx = Ws[sg][0], Wy = Ws[sg][1];
+      if (DIM == 2) {
+        const Real l10 = L[base], l11 = L[base + sy];
+        const Real l20 = L[cs + base], l21 = L[cs + base + 1];
+        Fb[sg][0] += C * (l10 * ((Real)1 - Wy) + l11 * Wy);
+        Wb[sg][1] += C * Fx * (l11 - l10);
+        Fb[sg][1] += C * (l20 * ((Real)1 - Wx) + l21 * Wx);
+        Wb[sg][0] += C * Fy * (l21 - l20);
+        const Real *L3 = L + 2 * cs + base;
+        const Real a00 = L3[0], a10 = L3[1], a01 = L3[sy], a11 = L3[sy + 1];
+        const Real h = C * dx3 * (Real)0.5;
+        const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
+        const Real val = a00 * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy) +
+                         a10 * (Wx * ((Real)1 - Wy) - cxy) + a01 * (((Real)1 - Wx) * Wy - cxy) +
+                         a11 * (Wx * Wy + cxy);
+        dx3b += C * (Real)0.5 * val;
+        Wb[sg][0] += h * (-a00 * ((Real)1 - Wy) + a10 * ((Real)1 - Wy) - a01 * Wy + a11 * Wy);
+        Wb[sg][1] += h * (-a00 * ((Real)1 - Wx) - a10 * Wx + a01 * ((Real)1 - Wx) + a11 * Wx);
+        const Real csum = (a00 - a10 - a01 + a11) * h * (Real)(1.0 / 12.0);
+        Fb[sg][0] += csum * Fy;
+        Fb[sg][1] += csum * Fx;
+      } else {
+        const Real Fz = Fs[sg][2], Wz = Ws[sg][2];
+        // component c with transverse dims (a, b): value = C F_c (w_a w_b + sgn F_a F_b / 12)
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+          const int da = (comp == 0) ? 1 : 0;
+          const int db = (comp == 2) ? 1 : 2;
+          const int sa = (da == 0) ? 1 : sy;
+          const int sb = (db == 1) ? sy : sz;
+          const Real *Lc = L + comp * cs + base;
+          const Real l00 = Lc[0], l10 = Lc[sa], l01 = Lc[sb], l11 = Lc[sa + sb];
+          const Real Fc = (comp == 0) ? Fx : (comp == 1 ? Fy : Fz);
+          const Real Wa = Ws[sg][da], Wbb = Ws[sg][db];
+          const Real Fa = Fs[sg][da], Fbt = Fs[sg][db];
+          const Real ga = (Real)1 - Wa, gb = (Real)1 - Wbb;
+          const Real cab = Fa * Fbt * (Real)(1.0 / 12.0);
+          const Real sgn = l00 - l10 - l01 + l11;
+          const Real val = l00 * (ga * gb + cab) + l10 * (Wa * gb - cab) + l01 * (ga * Wbb - cab) +
+                           l11 * (Wa * Wbb + cab);
+          Fb[sg][comp] += C * val;
+          Wb[sg][da] += C * Fc * (-l00 * gb + l10 * gb - l01 * Wbb + l11 * Wbb);
+          Wb[sg][db] += C * Fc * (-l00 * ga - l10 * Wa + l01 * ga + l11 * Wa);
+          Fb[sg][da] += C * Fc * sgn * Fbt * (Real)(1.0 / 12.0);
+          Fb[sg][db] += C * Fc * sgn * Fa * (Real)(1.0 / 12.0);
+        }
+        (void)Fz;
+        (void)Wz;
+      }
+    }
+    // relay: F1 = xr - a, F2 = b - xr, W1 = (a + xr)/2, W2 = (xr + b)/2 - m
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      Real xrb = Fb[0][a] - Fb[1][a] + (Real)0.5 * (Wb[0][a] + Wb[1][a]);
+      Real abar = -Fb[0][a] + (Real)0.5 * Wb[0][a];
+      Real bbar = Fb[1][a] + (Real)0.5 * Wb[1][a];
+      if (mid_free[a]) {  // xr = (a + b)/2
+        abar += (Real)0.5 * xrb;
+        bbar += (Real)0.5 * xrb;
+      }
+      // b = a + dx
+      ab[a] += abar + bbar;
+      dxb[a] += bbar;
+    }
+  }
+  // steps 6-7 reversed: dx_a = dt u_a / (gamma Delta_a); 2D also dx3 = dt u_z / gamma
+  Real wv[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) wv[a] = dxb[a] * dtr / (Real)g.dx[a];
+  if (DIM == 2) wv[2] = dx3b * dtr;
+  const Real uw = un[0] * wv[0] + un[1] * wv[1] + un[2] * wv[2];
+  Real unb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) unb[a] = A.lam_u[a][p] + wv[a] * ig - un[a] * uw * ig * ig * ig;
+  // step 5 reversed (Boris)
+  Real Eb[3], Bb[3], umb[3], upb[3], sb[3], tb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Eb[a] = k * unb[a];  // u+ = u+' + k E
+    umb[a] = unb[a];     // u+' = um + up x s
+  }
+  // up x s: upb += s x unb, sb = unb x up
+  upb[0] = s3[1] * unb[2] - s3[2] * unb[1];
+  upb[1] = s3[2] * unb[0] - s3[0] * unb[2];
+  upb[2] = s3[0] * unb[1] - s3[1] * unb[0];
+  sb[0] = unb[1] * up[2] - unb[2] * up[1];
+  sb[1] = unb[2] * up[0] - unb[0] * up[2];
+  sb[2] = unb[0] * up[1] - unb[1] * up[0];
+  // up = um + um x t: umb += upb + t x upb, tb = upb x um
+#pragma unroll
+  for (int a = 0; a < 3; ++a) umb[a] += upb[a];
+  umb[0] += t[1] * upb[2] - t[2] * upb[1];
+  umb[1] += t[2] * upb[0] - t[0] * upb[2];
+  umb[2] += t[0] * upb[1] - t[1] * upb[0];
+  tb[0] = upb[1] * um[2] - upb[2] * um[1];
+  tb[1] = upb[2] * um[0] - upb[0] * um[2];
+  tb[2] = upb[0] * um[1] - upb[1] * um[0];
+  // s = t sf, sf = 2 / (1 + t.t)
+  const Real ts = t[0] * sb[0] + t[1] * sb[1] + t[2] * sb[2];
+  const Real c4 = (Real)4 / (((Real)1 + tt) * ((Real)1 + tt));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) tb[a] += sf * sb[a] - c4 * t[a] * ts;
+  // t = k B / gm
+  Real gmb = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Bb[a] = k * igm * tb[a];
+    gmb -= t[a] * tb[a] * igm;
+  }
+  // gm = sqrt(1 + um.um); um = u + k E
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    umb[a] += gmb * um[a] * igm;
+    Eb[a] += k * umb[a];
+  }
+  // tetrad reversed and interpolation reversed (scatter + offset derivative)
+  Real Fbar[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fbar[a] = Eb[a] * sc[a];
+    Fbar[3 + a] = Bb[a] * sc[a];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
+    const int bx = sx ? st[0].bh : st[0].b0;
+    const int by = sy2 ? st[1].bh : st[1].b0;
+    const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
+    const Real fx = sx ? st[0].fh : st[0].f0;
+    const Real fy = sy2 ? st[1].fh : st[1].f0;
+    const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
+    Real cv[8];
+    int ix[8];
+    corners<DIM, Real>(A.EB + c * (int)g.npts, g, bx, by, bz, cv, ix);
+    const Real gx = (Real)1 - fx, gy = (Real)1 - fy, gz = (Real)1 - fz;
+    const Real fb = Fbar[c];
+    Real *dE = A.dEB + c * (int)g.npts;
+    if (DIM == 2) {
+      atomic_add_r(dE + ix[0], fb * gx * gy);
+      atomic_add_r(dE + ix[1], fb * fx * gy);
+      atomic_add_r(dE + ix[2], fb * gx * fy);
+      atomic_add_r(dE + ix[3], fb * fx * fy);
+      ab[0] += fb * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]));
+      ab[1] += fb * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]));
+    } else {
+      atomic_add_r(dE + ix[0], fb * gx * gy * gz);
+      atomic_add_r(dE + ix[1], fb * fx * gy * gz);
+      atomic_add_r(dE + ix[2], fb * gx * fy * gz);
+      atomic_add_r(dE + ix[3], fb * fx * fy * gz);
+      atomic_add_r(dE + ix[4], fb * gx * gy * fz);
+      atomic_add_r(dE + ix[5], fb * fx * gy * fz);
+      atomic_add_r(dE + ix[6], fb * gx * fy * fz);
+      atomic_add_r(dE + ix[7], fb * fx * fy * fz);
+      ab[0] += fb * (gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
+                     fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6])));
+      ab[1] += fb * (gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
+                     fz * (gx * (cv[6] - cv[4]) + fx * (cv[7] - cv[5])));
+      ab[2] += fb * (gy * (gx * (cv[4] - cv[0]) + fx * (cv[5] - cv[1])) +
+                     fy * (gx * (cv[6] - cv[2]) + fx * (cv[7] - cv[3])));
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.lam_u[a][p] = umb[a];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
+}
+
+template <class Real>
+hipError_t launch_adjoint_step(const AdjArgs<Real> &a, hipStream_t s) {
+  const int64_t nblk = a.sp.blk0[a.sp.nspec];
+  if (nblk == 0) return hipSuccess;
+  if (a.g.geom != 0) return hipErrorNotSupported;
+  dim3 grid((unsigned)nblk), block(BLOCK);
+  if (a.g.dim == 2)
+    hipLaunchKernelGGL((k_adjoint_cart<2, Real>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adjoint_cart<3, Real>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_adjoint_step<float>(const AdjArgs<float> &, hipStream_t);
+template hipError_t launch_adjoint_step<double>(const AdjArgs<double> &, hipStream_t);
+
+}  // namespace picstep

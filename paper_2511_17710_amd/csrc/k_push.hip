@@ -112,13 +112,56 @@ __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
   }
 }
 
+// q = x / d for 0 <= x < 2^23 with a float reciprocal and one correction
+__device__ __forceinline__ int div_small(int x, int d, float inv) {
+  int q = (int)((float)x * inv);
+  if (q * d > x) --q;
+  else if ((q + 1) * d <= x) ++q;
+  return q;
+}
+
+// block-wide sum of three ints (256 threads)
+__device__ __forceinline__ void block_sum3(int v[3], int *red) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v[d] += __shfl_xor(v[d], o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) red[w * 6 + d] = v[d];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    v[d] = 0;
+#pragma unroll
+    for (int ww = 0; ww < BLOCK / 64; ++ww) v[d] += red[ww * 6 + d];
+  }
+}
+
 // ---------------------------------------------------------------- per-particle steps
 // Cartesian: tetrad F^i_hat = Delta_i F^i (eq. curvspace-tetradtrans with the
 // Sec. 2.4 Cartesian metric, h33 = 1 in 2D); the basis is already global.
+// A particle deposits into the block's LDS tile when its whole stencil (cell
+// -1 ... cell +2 in every dimension, in the tile's unwrapped frame) lies
+// inside it, else straight into the global current.
+template <int DIM, class Real>
+__device__ __forceinline__ bool in_tile(const DepTarget<Real> &tile, const int ts[3],
+                                        const int ib[3]) {
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) in = in && (ib[a] - 1 >= tile.o[a]) && (ib[a] + 2 < tile.o[a] + ts[a]);
+  return in;
+}
+
 template <int DIM, class Real>
 __device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s, int32_t c,
                                                  OffT<Real> q[3], Real u[3], Real w,
-                                                 const DepTarget<Real> &tg, const int shift[3]) {
+                                                 const DepTarget<Real> &tile,
+                                                 const DepTarget<Real> &glob, const int ts[3],
+                                                 const int shift[3]) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -163,7 +206,15 @@ __device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s,
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
     if (shift[a] && i[a] < (g.n[a] >> 1)) ib[a] += g.n[a];
-  deposit<DIM, Real>(tg, (Real)A.sp.qdt[s] * w, ib, m, z, dx3);
+  if (A.deposit) {
+    const Real C = (Real)A.sp.qdt[s] * w;
+    if (in_tile<DIM, Real>(tile, ts, ib)) {
+      deposit<DIM, Real>(tile, C, ib, m, z, dx3);
+    } else {
+      deposit<DIM, Real>(glob, C, i, m, z, dx3);
+      if (A.stats) atomicAdd(A.stats + 1, 1);
+    }
+  }
   return cell_encode(g, inew);
 }
 
@@ -217,7 +268,8 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
 template <int GEOM, class Real>
 __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int32_t c,
                                             OffT<Real> q[3], Real u[3], Real w, Real &phi,
-                                            const DepTarget<Real> &tg) {
+                                            const DepTarget<Real> &tile,
+                                            const DepTarget<Real> &glob, const int ts[3]) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -266,7 +318,15 @@ __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int3
   const double zb[3] = {PS::exact(qn1) + (double)m[0], PS::exact(qn2) + (double)m[1], 0.0};
   ZigZag<Real> z;
   zigzag<2, Real>(za, m, zb, z);
-  deposit<2, Real>(tg, (Real)A.sp.qdt[s] * w, i, m, z, dx3);
+  if (A.deposit) {
+    const Real C = (Real)A.sp.qdt[s] * w;
+    if (in_tile<2, Real>(tile, ts, i)) {
+      deposit<2, Real>(tile, C, i, m, z, dx3);
+    } else {
+      deposit<2, Real>(glob, C, i, m, z, dx3);
+      if (A.stats) atomicAdd(A.stats + 1, 1);
+    }
+  }
   q[0] = qn1;
   q[1] = qn2;
   phi = phinew;
@@ -278,17 +338,19 @@ template <int GEOM, int DIM, class Real>
 __device__ __forceinline__ void push_particles(const StepArgs<Real> &A, int s, int cnt,
                                                int32_t cl[PPT], OffT<Real> qd[3][PPT],
                                                Real uu[3][PPT], const Real ww[PPT], Real ph[PPT],
-                                               const DepTarget<Real> &tg, const int shift[3]) {
+                                               const DepTarget<Real> &tile,
+                                               const DepTarget<Real> &glob, const int ts[3],
+                                               const int shift[3]) {
   for (int r = 0; r < PPT; ++r) {
     if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
     OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
                        DIM > 2 ? qd[2][r] : (OffT<Real>)0};
     Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
     if (GEOM == 0) {
-      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tg, shift);
+      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tile, glob, ts, shift);
     } else {
       Real p = ph[r];
-      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tg);
+      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tile, glob, ts);
       ph[r] = p;
     }
 #pragma unroll
@@ -368,17 +430,42 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
       block_minmax3(lo, hi, red);
     }
   }
+  // tile placement: the whole box when it fits, else the largest cube (square
+  // in 2D) centred on the chunk's mean cell; particles whose stencil leaves
+  // the tile deposit with global atomics
   int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1};
+  int64_t T = 1;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    t0[d] = lo[d] - 1;  // stencils reach cell - 1 ... cell + 2
-    ts[d] = hi[d] - lo[d] + 4;
+    ts[d] = hi[d] - lo[d] + 4;  // stencils reach cell - 1 ... cell + 2
+    T *= ts[d];
   }
-  const int64_t T = (int64_t)ts[0] * ts[1] * ts[2];
-  const bool use_tile = 3 * T <= TILE_VALS;
-  if (A.stats && threadIdx.x == 0) {
-    atomicAdd(A.stats, 1);
-    if (!use_tile) atomicAdd(A.stats + 1, 1);
+  if (3 * T <= TILE_VALS) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) t0[d] = lo[d] - 1;
+  } else {
+    __syncthreads();
+    int sum[3] = {0, 0, 0}, nl[3] = {0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      if (cl[r] & DEAD_BIT) continue;
+      nl[0] += 1;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        sum[d] += ic[r][d] + ((shift[d] && ic[r][d] < (g.n[d] >> 1)) ? g.n[d] : 0);
+    }
+    block_sum3(sum, red);
+    __syncthreads();
+    block_sum3(nl, red);
+    constexpr int SIDE = (DIM == 3) ? ((sizeof(Real) == 4) ? 13 : 11) : ((sizeof(Real) == 4) ? 52 : 36);
+    T = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int ctr = (sum[d] + nl[0] / 2) / nl[0];
+      ts[d] = SIDE;
+      t0[d] = ctr - SIDE / 2 - 1;
+      T *= ts[d];
+    }
   }
 
   Real uu[3][PPT], ww[PPT], ph[PPT];
@@ -387,30 +474,28 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
   load_n(A.p.w + p0, cnt, ww, (Real)0);
   if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
 
+  const bool use_tile = A.deposit != 0;
+  if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
+  DepTarget<Real> tile_t, glob_t;
+  tile_t.J = tile;
+  tile_t.cs = (int)T;
+  tile_t.sy = ts[0];
+  tile_t.sz = ts[0] * ts[1];
+  tile_t.o[0] = t0[0];
+  tile_t.o[1] = t0[1];
+  tile_t.o[2] = t0[2];
+  glob_t.J = A.J;
+  glob_t.cs = (int)g.npts;
+  glob_t.sy = g.np[0];
+  glob_t.sz = g.np[0] * g.np[1];
+  glob_t.o[0] = -NG;
+  glob_t.o[1] = -NG;
+  glob_t.o[2] = (DIM == 3) ? -NG : 0;
   if (use_tile) {
-    for (int64_t x = threadIdx.x; x < 3 * T; x += BLOCK) tile[x] = (Real)0;
+    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Real)0;
     __syncthreads();
-    DepTarget<Real> tg;
-    tg.J = tile;
-    tg.cs = T;
-    tg.sy = ts[0];
-    tg.sz = (int64_t)ts[0] * ts[1];
-    tg.o[0] = t0[0];
-    tg.o[1] = t0[1];
-    tg.o[2] = t0[2];
-    push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tg, shift);
-  } else {
-    DepTarget<Real> tg;
-    tg.J = A.J;
-    tg.cs = g.npts;
-    tg.sy = g.np[0];
-    tg.sz = (int64_t)g.np[0] * g.np[1];
-    tg.o[0] = -NG;
-    tg.o[1] = -NG;
-    tg.o[2] = (DIM == 3) ? -NG : 0;
-    const int noshift[3] = {0, 0, 0};
-    push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tg, noshift);
   }
+  push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tile_t, glob_t, ts, shift);
 
   store_n(A.p.cell + p0, cnt, cl);
 #pragma unroll
@@ -421,23 +506,25 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
 
   if (use_tile) {
     __syncthreads();
-    const int64_t np0 = g.np[0], np01 = np0 * g.np[1];
-    for (int64_t x = threadIdx.x; x < 3 * T; x += BLOCK) {
+    const int Ti = (int)T, ts0 = ts[0], ts01 = ts[0] * ts[1];
+    const float iT = 1.0f / (float)Ti, i0f = 1.0f / (float)ts0, i01 = 1.0f / (float)ts01;
+    const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
+    for (int x = threadIdx.x; x < 3 * Ti; x += BLOCK) {
       const Real v = tile[x];
       if (v == (Real)0) continue;
-      const int64_t comp = x / T;
-      int64_t rem = x - comp * T;
-      const int ix = (int)(rem % ts[0]);
-      rem /= ts[0];
-      const int iy = (int)(rem % ts[1]);
-      const int iz = (int)(rem / ts[1]);
+      const int comp = div_small(x, Ti, iT);
+      int rem = x - comp * Ti;
+      const int iz = div_small(rem, ts01, i01);
+      rem -= iz * ts01;
+      const int iy = div_small(rem, ts0, i0f);
+      const int ix = rem - iy * ts0;
       int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
       if (GEOM == 0) {  // periodic: add straight into the image in the active region
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) gi[d] = (gi[d] + 2 * g.n[d]) % g.n[d];
+        for (int d = 0; d < DIM; ++d) gi[d] = ((gi[d] % g.n[d]) + g.n[d]) % g.n[d];
       }
-      const int64_t gidx = comp * g.npts + (int64_t)(gi[0] + NG) + np0 * (int64_t)(gi[1] + NG) +
-                           ((DIM == 3) ? np01 * (int64_t)(gi[2] + NG) : 0);
+      const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
+                       ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
       atomic_add_r(A.J + gidx, v);
     }
   }

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(UT) void k_fill_ghosts(GridConst g, Real *A, int nc
   int s = v % g.n[dd];
   if (s < 0) s += g.n[dd];
   ii[dd] = s;
-  A[q] = A[c * g.npts + pad_index(g, ii[0], ii[1], ii[2], g.dim)];
+  A[q] = A[c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim)];
 }
 
 // add every ghost point of dimension dd into its periodic image, zero the ghost
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(UT) void k_fold_ghosts(GridConst g, Real *A, int nc
   int s = v % g.n[dd];
   if (s < 0) s += g.n[dd];
   ii[dd] = s;
-  atomic_add_r(A + c * g.npts + pad_index(g, ii[0], ii[1], ii[2], g.dim), x);
+  atomic_add_r(A + c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim), x);
 }
 
 template <class Real>

@@ -55,6 +55,8 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   int64_t step = 0;
   double dx_min = 0;  // Sec. 2.4 CFL length
+  int32_t ckpt_K = -1, ckpt_m = -1;  // last pic_forward_checkpointed
+  int64_t ckpt_step0 = 0;
   bool timing = false;
   struct Ev {
     hipEvent_t a, b;
@@ -196,7 +198,7 @@ pic_status do_sort(pic_ctx *c) {
 }
 
 template <class Real>
-pic_status do_step(pic_ctx *c, double dt, bool write_prev) {
+pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   StepArgs<Real> a{};
   a.g = c->g;
   a.sp = species_table(c, dt, PUSH_CHUNK);
@@ -208,14 +210,16 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev) {
   a.J = reinterpret_cast<Real *>(c->current);
   a.dt = dt;
   a.write_prev = write_prev ? 1 : 0;
+  a.deposit = dep ? 1 : 0;
   a.stats = c->timing ? reinterpret_cast<int32_t *>(c->scratch + c->s_stats) : nullptr;
-  hipError_t e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
+  hipError_t e = hipSuccess;
+  if (dep) e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "zero J");
-  const int ev = ev_begin(c, 0);
+  const int ev = dep ? ev_begin(c, 0) : -1;
   e = launch_push_deposit<Real>(a, c->stream);
   ev_end(c, ev);
   if (e != hipSuccess) return hipchk(c, e, "push_deposit");
-  e = launch_fold_ghosts<Real>(c->g, a.J, 3, c->stream);
+  if (dep) e = launch_fold_ghosts<Real>(c->g, a.J, 3, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "fold J");
   return PIC_OK;
 }
@@ -235,6 +239,161 @@ pic_status run_steps(pic_ctx *c, double dt, int32_t n, bool allow_sort) {
 }
 
 bool isfin(double x) { return std::isfinite(x); }
+
+// ---- adjoint workspace: checkpoints, one segment of stored states, adjoints
+struct AdjLayout {
+  uint64_t slot, nck, seg, ckpt0, seg0, lam_u, lam_d, lamJ, total;
+};
+
+AdjLayout adj_layout(const pic_ctx *c, int32_t K, int32_t m) {
+  AdjLayout L{};
+  const uint64_t ab = align_up(c->capacity * c->eb, ALIGN);
+  L.slot = align_up(c->ckpt_bytes, ALIGN);
+  L.nck = (uint64_t)((K + m - 1) / m);
+  L.seg = (uint64_t)std::min(K, m);
+  L.ckpt0 = 0;
+  L.seg0 = L.nck * L.slot;
+  L.lam_u = L.seg0 + L.seg * L.slot;
+  L.lam_d = L.lam_u + 3 * ab;
+  L.lamJ = L.lam_d + 3 * ab;
+  L.total = L.lamJ + align_up(3ull * c->g.npts * c->eb, ALIGN);
+  return L;
+}
+
+// a checkpoint slot holds cell, offsets, u (and phi) of the whole capacity
+template <class Real>
+PSet<Real> slot_pset(const pic_ctx *c, char *slot) {
+  const uint64_t ai = align_up(c->capacity * 4, ALIGN), ab = align_up(c->capacity * c->eb, ALIGN);
+  PSet<Real> p{};
+  uint64_t o = 0;
+  p.cell = reinterpret_cast<int32_t *>(slot + o);
+  o += ai;
+  for (int a = 0; a < 3; ++a) {
+    p.offs[a] = nullptr;
+    if (a < c->g.dim) {
+      p.offs[a] = reinterpret_cast<OffT<Real> *>(slot + o);
+      o += ab;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    p.u[a] = reinterpret_cast<Real *>(slot + o);
+    o += ab;
+  }
+  p.phi = nullptr;
+  if (c->g.geom != 0) p.phi = reinterpret_cast<Real *>(slot + o);
+  p.w = nullptr;
+  return p;
+}
+
+template <class Real>
+hipError_t copy_state(const pic_ctx *c, const PSet<Real> &dst, const PSet<Real> &src) {
+  const uint64_t n = c->capacity;
+  hipError_t e = hipMemcpyAsync(dst.cell, src.cell, n * 4, hipMemcpyDeviceToDevice, c->stream);
+  for (int a = 0; a < c->g.dim && e == hipSuccess; ++a)
+    e = hipMemcpyAsync(dst.offs[a], src.offs[a], n * sizeof(OffT<Real>), hipMemcpyDeviceToDevice, c->stream);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    e = hipMemcpyAsync(dst.u[a], src.u[a], n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && c->g.geom != 0)
+    e = hipMemcpyAsync(dst.phi, src.phi, n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+  return e;
+}
+
+template <class Real>
+pic_status fwd_ckpt(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws) {
+  const AdjLayout L = adj_layout(c, K, m);
+  c->ckpt_K = K;
+  c->ckpt_m = m;
+  c->ckpt_step0 = c->step;
+  for (int32_t n = 0; n < K; ++n) {
+    if (n % m == 0) {
+      hipError_t e = copy_state<Real>(c, slot_pset<Real>(c, ws + L.ckpt0 + (n / m) * L.slot),
+                                      pset_of<Real>(c, c->active));
+      if (e != hipSuccess) return hipchk(c, e, "checkpoint save");
+    }
+    pic_status st = do_step<Real>(c, dt, n == K - 1, true);
+    if (st != PIC_OK) return st;
+    c->step += 1;
+  }
+  return PIC_OK;
+}
+
+template <class Real>
+pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void *lamJ,
+               const void *lam_u, void *dEB, void *du0) {
+  const AdjLayout L = adj_layout(c, K, m);
+  const GridConst &g = c->g;
+  const uint64_t cap = c->capacity;
+  const uint64_t ab = align_up(cap * c->eb, ALIGN);
+  Real *lu[3], *ld[3];
+  for (int a = 0; a < 3; ++a) {
+    lu[a] = reinterpret_cast<Real *>(ws + L.lam_u + a * ab);
+    ld[a] = reinterpret_cast<Real *>(ws + L.lam_d + a * ab);
+  }
+  Real *lJ = reinterpret_cast<Real *>(ws + L.lamJ);
+  Real *dE = static_cast<Real *>(dEB);
+  hipError_t e = launch_zero<Real>(dE, 6 * g.npts, c->stream);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+    if (lam_u)
+      e = hipMemcpyAsync(lu[a], static_cast<const Real *>(lam_u) + a * cap, cap * sizeof(Real),
+                         hipMemcpyDeviceToDevice, c->stream);
+    else
+      e = launch_zero<Real>(lu[a], (int64_t)cap, c->stream);
+    if (e == hipSuccess) e = launch_zero<Real>(ld[a], (int64_t)cap, c->stream);
+  }
+  if (e == hipSuccess && lamJ) {
+    // a deposit into a periodic ghost ends up in its image: gather from there
+    e = hipMemcpyAsync(lJ, lamJ, 3ull * g.npts * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_ghosts<Real>(g, lJ, 3, c->stream);
+  }
+  if (e != hipSuccess) return hipchk(c, e, "backward setup");
+  const PSet<Real> act = pset_of<Real>(c, c->active);
+  AdjArgs<Real> A{};
+  A.g = g;
+  A.sp = species_table(c, dt, BLOCK);
+  A.EB = reinterpret_cast<const Real *>(c->fields);
+  A.dEB = dE;
+  A.dt = dt;
+  for (int a = 0; a < 3; ++a) {
+    A.lam_u[a] = lu[a];
+    A.lam_d[a] = ld[a];
+  }
+  A.lam_phi = nullptr;
+  const int64_t saved_step = c->step;
+  for (int64_t j = (int64_t)L.nck - 1; j >= 0; --j) {
+    const int32_t s0 = (int32_t)(j * m), s1 = std::min(K, s0 + m);
+    e = copy_state<Real>(c, act, slot_pset<Real>(c, ws + L.ckpt0 + j * L.slot));
+    if (e != hipSuccess) return hipchk(c, e, "checkpoint load");
+    for (int32_t n = s0; n < s1; ++n) {
+      e = copy_state<Real>(c, slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot), act);
+      if (e != hipSuccess) return hipchk(c, e, "segment store");
+      if (n < s1 - 1) {
+        pic_status st = do_step<Real>(c, dt, false, false);
+        if (st != PIC_OK) return st;
+      }
+    }
+    for (int32_t n = s1 - 1; n >= s0; --n) {
+      PSet<Real> st = slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot);
+      st.w = act.w;
+      A.p = st;
+      A.lamJ = (n == K - 1 && lamJ) ? lJ : nullptr;
+      const int ev = ev_begin(c, 2);
+      e = launch_adjoint_step<Real>(A, c->stream);
+      ev_end(c, ev);
+      if (e != hipSuccess) return hipchk(c, e, "adjoint step");
+    }
+  }
+  e = launch_fold_ghosts<Real>(g, dE, 6, c->stream);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    e = hipMemcpyAsync(static_cast<Real *>(du0) + a * cap, lu[a], cap * sizeof(Real),
+                       hipMemcpyDeviceToDevice, c->stream);
+  // leave the particles as they were at step 0 of the checkpointed run
+  if (e == hipSuccess) e = copy_state<Real>(c, act, slot_pset<Real>(c, ws + L.ckpt0));
+  if (e != hipSuccess) return hipchk(c, e, "backward finish");
+  (void)saved_step;
+  c->step = c->ckpt_step0;
+  return PIC_OK;
+}
+
 
 uint32_t offset_to_fixed(double d) {
   const double r = std::nearbyint(d * 4294967296.0);
@@ -303,6 +462,10 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
     g.dx[a] = (d.geom == PIC_CART && a < d.dim) ? (d.hi[a] - d.lo[a]) / d.n[a] : 1.0;
   }
   g.npts = (int64_t)g.np[0] * g.np[1] * g.np[2];
+  if (6 * g.npts >= (int64_t(1) << 31)) {  // device index math is 32-bit
+    delete c;
+    return PIC_E_UNSUPPORTED;
+  }
   g.rmin = d.lo[0];
   g.dr = (d.geom != PIC_CART) ? (d.hi[0] - d.lo[0]) / d.n[0] : 0.0;
   g.dth = (d.geom != PIC_CART) ? PI / d.n[1] : 0.0;
@@ -787,21 +950,28 @@ pic_status pic_timing_read(pic_ctx *c, pic_timing *out) {
 
 pic_status pic_adjoint_workspace(const pic_ctx *c, int32_t K, int32_t m, uint64_t *bytes) {
   if (!c || !bytes || K < 1 || m < 1) return PIC_E_ARG;
-  const uint64_t nck = (uint64_t)((K + m - 1) / m);
-  const uint64_t seg = (uint64_t)std::min(K, m);
-  // checkpoints + per-step states of one segment + adjoint state (u, offs, phi)
-  const uint64_t ab = align_up(c->capacity * c->eb, ALIGN);
-  *bytes = (nck + seg) * align_up(c->ckpt_bytes, ALIGN) + 6 * ab;
+  *bytes = adj_layout(c, K, m).total;
   return PIC_OK;
 }
 
-pic_status pic_forward_checkpointed(pic_ctx *c, double, int32_t, int32_t, void *) {
-  return fail(c, PIC_E_UNSUPPORTED, "adjoint not built yet");
+pic_status pic_forward_checkpointed(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws) {
+  if (!c || !ws || K < 1 || m < 1) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "forward before bind/fields_set");
+  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
+  if (!(dt > 0) || dt > c->dx_min) return fail(c, PIC_E_ARG, "bad dt");
+  return c->eb == 8 ? fwd_ckpt<double>(c, dt, K, m, static_cast<char *>(ws))
+                    : fwd_ckpt<float>(c, dt, K, m, static_cast<char *>(ws));
 }
 
-pic_status pic_backward(pic_ctx *c, double, int32_t, int32_t, void *, const void *, const void *,
-                        void *, void *) {
-  return fail(c, PIC_E_UNSUPPORTED, "adjoint not built yet");
+pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, const void *lamJ,
+                        const void *lam_u, void *dEB, void *du0) {
+  if (!c || !ws || !dEB || !du0 || K < 1 || m < 1) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "backward before bind/fields_set");
+  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
+  if (c->ckpt_K != K || c->ckpt_m != m)
+    return fail(c, PIC_E_STATE, "backward(K=%d, m=%d) without a matching forward_checkpointed", K, m);
+  return c->eb == 8 ? bwd<double>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0)
+                    : bwd<float>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0);
 }
 
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -54,9 +54,10 @@ __device__ __forceinline__ bool locate(const SpeciesTable &sp, int &s, int64_t &
   return local < sp.n[s];
 }
 
-__device__ __forceinline__ int64_t pad_index(const GridConst &g, int i, int j, int k, int dim) {
-  const int64_t kk = (dim == 3) ? (int64_t)(k + NG) : 0;
-  return (int64_t)(i + NG) + (int64_t)g.np[0] * ((int64_t)(j + NG) + (int64_t)g.np[1] * kk);
+// padded element index (the host guarantees 6 * npts < 2^31)
+__device__ __forceinline__ int pad_index(const GridConst &g, int i, int j, int k, int dim) {
+  const int kk = (dim == 3) ? (k + NG) : 0;
+  return (i + NG) + g.np[0] * ((j + NG) + g.np[1] * kk);
 }
 
 // ---------------------------------------------------------------- step 3: interpolation
@@ -93,12 +94,12 @@ __device__ constexpr int kStag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1},
 template <int DIM, class Real>
 __device__ __forceinline__ Real gather_one(const Real *__restrict__ A, const GridConst &g, int bx,
                                            int by, int bz, Real fx, Real fy, Real fz) {
-  const int64_t np0 = g.np[0];
-  const int64_t base = pad_index(g, bx, by, bz, DIM);
+  const int np0 = g.np[0];
+  const int base = pad_index(g, bx, by, bz, DIM);
   const Real gx = (Real)1 - fx, gy = (Real)1 - fy;
   Real v = gy * (gx * A[base] + fx * A[base + 1]) + fy * (gx * A[base + np0] + fx * A[base + np0 + 1]);
   if (DIM == 3) {
-    const int64_t np01 = np0 * g.np[1];
+    const int np01 = np0 * g.np[1];
     Real v1 = gy * (gx * A[base + np01] + fx * A[base + np01 + 1]) +
               fy * (gx * A[base + np01 + np0] + fx * A[base + np01 + np0 + 1]);
     v = ((Real)1 - fz) * v + fz * v1;
@@ -118,7 +119,7 @@ __device__ __forceinline__ void interp6(const Real *__restrict__ EB, const GridC
     const Real fx = sx ? st[0].fh : st[0].f0;
     const Real fy = sy ? st[1].fh : st[1].f0;
     const Real fz = (DIM == 3) ? (sz ? st[2].fh : st[2].f0) : (Real)0;
-    F[c] = gather_one<DIM, Real>(EB + (int64_t)c * g.npts, g, bx, by, bz, fx, fy, fz);
+    F[c] = gather_one<DIM, Real>(EB + c * (int)g.npts, g, bx, by, bz, fx, fy, fz);
   }
 }
 
@@ -237,7 +238,7 @@ __device__ __forceinline__ void atomic_add_r(double *p, double v) { unsafeAtomic
 template <class Real>
 struct DepTarget {
   Real *J;
-  int64_t cs, sy, sz;
+  int cs, sy, sz;
   int o[3];
 };
 
@@ -246,13 +247,13 @@ struct DepTarget {
 template <int DIM, class Real>
 __device__ __forceinline__ void deposit(const DepTarget<Real> &t, Real C, const int i0[3],
                                         const int m[3], const ZigZag<Real> &z, Real dx3) {
-  const int64_t cs = t.cs, sy = t.sy, sz = t.sz;
+  const int cs = t.cs, sy = t.sy, sz = t.sz;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const int I = i0[0] + (s ? m[0] : 0) - t.o[0];
     const int Jc = i0[1] + (s ? m[1] : 0) - t.o[1];
     const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) - t.o[2] : 0;
-    const int64_t base = (int64_t)I + sy * (int64_t)Jc + sz * (int64_t)K;
+    const int base = I + sy * Jc + sz * K;
     const Real Fx = z.F[s][0], Fy = z.F[s][1];
     const Real Wx = z.W[s][0], Wy = z.W[s][1];
     if (DIM == 2) {

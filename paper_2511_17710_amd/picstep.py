@@ -251,6 +251,49 @@ class Context:
         self._check(lib().pic_step_count(self.h, C.byref(v)), "step_count")
         return v.value
 
+    # -------------------------------------------------------------- adjoint
+    def adjoint_workspace(self, K, m):
+        nb = C.c_uint64()
+        self._check(lib().pic_adjoint_workspace(self.h, int(K), int(m), C.byref(nb)),
+                    "adjoint_workspace")
+        return nb.value
+
+    def forward_checkpointed(self, dt, K, m):
+        """K steps without sorting; the state is kept every m steps in a
+        torch-allocated workspace for backward()."""
+        nb = self.adjoint_workspace(K, m)
+        ws = getattr(self, "_ws", None)
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            self._ws = ws
+        self._check(lib().pic_forward_checkpointed(self.h, float(dt), int(K), int(m),
+                                                   C.c_void_p(ws.data_ptr())), "forward_checkpointed")
+
+    def backward(self, dt, K, m, lamJ=None, lam_u=None):
+        """dL/d(fields) [6, np3, np2, np1] and dL/du0 [3, capacity] for
+        L = sum(lamJ * J_K) + sum(lam_u * u_K)."""
+        cap = self.layout().capacity
+        dEB = torch.empty((6,) + self.padded_shape(), dtype=self.dtype, device=self.device)
+        du0 = torch.empty((3, cap), dtype=self.dtype, device=self.device)
+
+        def ptr(t, shape):
+            if t is None:
+                return None
+            t = t.to(device=self.device, dtype=self.dtype).contiguous()
+            assert tuple(t.shape) == tuple(shape), (t.shape, shape)
+            keep.append(t)
+            return C.c_void_p(t.data_ptr())
+
+        keep = []
+        pJ = ptr(lamJ, (3,) + self.padded_shape())
+        pu = ptr(lam_u, (3, cap))
+        self._check(lib().pic_backward(self.h, float(dt), int(K), int(m),
+                                       C.c_void_p(self._ws.data_ptr()), pJ, pu,
+                                       C.c_void_p(dEB.data_ptr()), C.c_void_p(du0.data_ptr())),
+                    "backward")
+        torch.cuda.current_stream(self.device).synchronize()
+        return dEB, du0
+
     def timing_enable(self, on=True):
         self._check(lib().pic_timing_enable(self.h, 1 if on else 0), "timing_enable")
 

@@ -1,0 +1,166 @@
+"""GPU adjoint of the K-step particle map (Cartesian grids) against the FP64
+reference adjoint, against central finite differences of the GPU forward, and
+through torch.autograd."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2511_17710_amd import workloads as W
+from tests import parity_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(dim, K, seed):
+    if dim == 2:
+        wl = W.cart2d(n=16, ppc=4, steps=K, seed=seed)
+    else:
+        wl = W.cart3d(n=8, ppc=2, steps=K, nwaves=8, seed=seed)
+    return wl
+
+
+def _weights(wl, seed):
+    rng = np.random.default_rng(seed)
+    shp = (3,) + wl.padded_shape()
+    lamJ = np.zeros(shp)
+    sl = [slice(None)] + [slice(2, 2 + wl.n[d]) if d < wl.dim else slice(None) for d in (2, 1, 0)]
+    lamJ[tuple(sl)] = rng.uniform(-1, 1, size=lamJ[tuple(sl)].shape)
+    lam_u = [rng.normal(size=(s["cell"].shape[0], 3)) for s in wl.species]
+    return lamJ, lam_u
+
+
+def _gpu_grad(wl, prec, K, m, lamJ, lam_u):
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    ctx = P.from_workload(wl, prec=prec, sort_every=0)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    ctx.forward_checkpointed(dt, K, m)
+    J = ctx.current_host().astype(np.float64)
+    L = ctx.layout()
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    lu = torch.zeros((3, L.capacity), dtype=dtype, device="cuda")
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        lu[:, o:o + lam.shape[0]] = torch.from_numpy(lam.T.copy()).to(dtype=dtype, device="cuda")
+    dEB, du0 = ctx.backward(dt, K, m, torch.from_numpy(lamJ).to(dtype=dtype, device="cuda"), lu)
+    dEB = dEB.double().cpu().numpy()
+    du0 = du0.double().cpu().numpy()
+    du = [du0[:, L.species_offset[s]:L.species_offset[s] + lam.shape[0]].T
+          for s, lam in enumerate(lam_u)]
+    return dEB, du, J, ctx, dt
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dim,K,m", [(2, 1, 1), (3, 1, 1), (2, 4, 2), (3, 4, 2)])
+def test_adjoint_matches_reference(dim, K, m, prec):
+    print(f"[adjoint] dim={dim} K={K} m={m} {prec}", flush=True)
+    wl = _case(dim, K, 40 + dim)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    lamJ, lam_u = _weights(wl, 7)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    ref = O.adjoint(g, dt, K, EB, wl.species, lamJ, lam_u=lam_u)
+    dEB, du, J, ctx, _ = _gpu_grad(wl, prec, K, m, lamJ, lam_u)
+    _, Jref = O.run(g, dt, K, EB, wl.species)
+    eJ = U.rel_l2(J, Jref)
+    eE = U.rel_l2(dEB, ref["dEB"])
+    eu = U.rel_l2(np.concatenate(du), np.concatenate(ref["du0"]))
+    print(f"  J {eJ:.2e} dEB {eE:.2e} du0 {eu:.2e}", flush=True)
+    tol = (1e-12 if K == 1 else 1e-10) if prec == "f64" else (1e-5 if K == 1 else 1e-3)
+    assert eJ < max(tol, 1e-5 if prec == "f32" else tol)
+    assert eE < tol, eE
+    assert eu < tol, eu
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    """Recomputing from checkpoints reproduces the stored trajectory exactly:
+    du0 is bitwise equal for m = K and m = 1; dEB agrees up to the order of
+    the atomic sums."""
+    print("[adjoint] checkpoint invariance", flush=True)
+    K = 6
+    wl = _case(3, K, 44)
+    lamJ, lam_u = _weights(wl, 8)
+    a = _gpu_grad(wl, "f64", K, K, lamJ, lam_u)
+    b = _gpu_grad(wl, "f64", K, 1, lamJ, lam_u)
+    for x, y in zip(a[1], b[1]):
+        np.testing.assert_array_equal(x, y)
+    assert U.rel_l2(a[0], b[0]) < 1e-13
+
+
+def test_adjoint_central_differences_16cube():
+    """The 16^3 subcase (65,536 particles, FP64): <grad, v> against central
+    differences of the GPU forward map along random directions."""
+    import torch
+    print("[adjoint] 16^3 finite differences", flush=True)
+    K, m = 8, 4
+    wl = W.by_name("cart3d_16_fd", K=K, ckpt=m)
+    rng = np.random.default_rng(9)
+    lamJ = wl.W
+    lam_u = [rng.normal(size=(s["cell"].shape[0], 3)) for s in wl.species]
+    dEB, du, _, ctx, dt = _gpu_grad(wl, "f64", K, m, lamJ, lam_u)
+    g, EB0 = U.oracle_fields(wl, "f64")
+    mask = np.zeros_like(EB0, dtype=bool)
+    mask[:, 2:18, 2:18, 2:18] = True
+    L = ctx.layout()
+
+    def loss(EBx, du_dir, h):
+        from paper_2511_17710_amd import picstep as P
+        c = P.from_workload(wl, prec="f64", sort_every=0)
+        c.fields().copy_(torch.from_numpy(EBx).cuda())
+        c.fields_fill_ghosts()
+        arr = c.particle_arrays()
+        for s, d in enumerate(du_dir):
+            o = L.species_offset[s]
+            for a in range(3):
+                arr["u"][a][o:o + d.shape[0]] += torch.from_numpy(h * d[:, a]).cuda()
+        c.push_deposit(dt, K)
+        J = c.current_host()
+        uu = [c.particles_get(s)["u"] for s in range(len(wl.species))]
+        return float(np.sum(lamJ * J) + sum(np.sum(l * x) for l, x in zip(lam_u, uu)))
+
+    # The first-order shape has kinks (relay clamp, half-cell stagger switch):
+    # with 65,536 particles x 8 steps a perturbation of 1e-6 carries about one
+    # trajectory across a kink (1e-5 relative error); 1e-8 makes that unlikely
+    # while FP64 round-off of the difference stays near 3e-7.
+    for trial in range(2):
+        vE = rng.normal(size=EB0.shape) * mask
+        vu = [rng.normal(size=(s["cell"].shape[0], 3)) for s in wl.species]
+        h = 1e-8
+        fd = (loss(EB0 + h * vE, vu, h) - loss(EB0 - h * vE, vu, -h)) / (2 * h)
+        ip = np.sum(dEB * vE) + sum(np.sum(a * b) for a, b in zip(du, vu))
+        print(f"  trial {trial}: grad.v {ip:.10e} fd {fd:.10e}", flush=True)
+        assert ip == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_autograd_function_matches_direct_backward():
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    from paper_2511_17710_amd.autograd import PushDeposit
+    print("[adjoint] autograd", flush=True)
+    K, m = 3, 2
+    wl = _case(3, K, 45)
+    lamJ, lam_u = _weights(wl, 10)
+    ref = _gpu_grad(wl, "f64", K, m, lamJ, lam_u)
+    ctx = P.from_workload(wl, prec="f64", sort_every=0)
+    g, EB = U.oracle_fields(wl, "f64")
+    dt = O.dt_from_cfl(g, wl.cfl)
+    L = ctx.layout()
+    EBt = torch.from_numpy(EB).cuda().requires_grad_(True)
+    arr = ctx.particle_arrays()
+    u0 = torch.stack([arr["u"][a].clone() for a in range(3)]).requires_grad_(True)
+    J, uK = PushDeposit.apply(EBt, u0, ctx, dt, K, m)
+    lu = torch.zeros_like(uK)
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        lu[:, o:o + lam.shape[0]] = torch.from_numpy(lam.T.copy()).cuda()
+    loss = (J * torch.from_numpy(lamJ).cuda()).sum() + (uK * lu).sum()
+    loss.backward()
+    np.testing.assert_allclose(EBt.grad.cpu().numpy(), ref[0], rtol=0, atol=1e-12 * np.abs(ref[0]).max())
+    du0 = u0.grad.cpu().numpy()
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        np.testing.assert_array_equal(du0[:, o:o + lam.shape[0]].T, ref[1][s])
