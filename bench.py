@@ -41,7 +41,7 @@ def run_gpu(wl, prec, steps, warmup, log):
 
     from paper_2511_17710_amd import picstep as P
     t0 = time.time()
-    ctx = P.from_workload(wl, prec=prec)
+    ctx = P.from_workload(wl, prec=prec, sort_every=wl.sort_every)
     dt = ctx.timestep_from_cfl(wl.cfl)
     torch.cuda.synchronize()
     log(f"[bench] {prec}: loaded {wl.nparticles} particles in {time.time() - t0:.1f}s, dt={dt:.6g}")
@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--sort-every", type=int, default=None,
+                    help="override the workload's sort cadence (steps)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -159,6 +161,8 @@ def main():
     from paper_2511_17710_amd import workloads as W
     t0 = time.time()
     wl = W.by_name(args.workload)
+    if args.sort_every is not None:
+        wl.sort_every = args.sort_every
     log(f"[bench] inputs {wl.name}: {wl.nparticles} particles in {time.time() - t0:.1f}s")
     ncells = int(np.prod(wl.n[:wl.dim]))
     has_phi = wl.geom != "cart"

@@ -35,7 +35,7 @@ def build(verbose=False):
         if verbose and msgs:
             print(msgs)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + [o for o, _ in res]
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", "-Wl,--no-undefined", "-o", tmp] + [o for o, _ in res]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -81,8 +81,8 @@ __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int
   return c0 < sp.n[s];
 }
 
-// block-wide min/max of three ints (256 threads)
-__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
+// block-wide min/max of three ints and max of a fourth (256 threads)
+__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int &x, int *red) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -91,13 +91,16 @@ __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
       hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
     }
   }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      red[w * 6 + d] = lo[d];
-      red[w * 6 + 3 + d] = hi[d];
+      red[w * 7 + d] = lo[d];
+      red[w * 7 + 3 + d] = hi[d];
     }
+    red[w * 7 + 6] = x;
   }
   __syncthreads();
 #pragma unroll
@@ -106,10 +109,13 @@ __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
     hi[d] = red[3 + d];
 #pragma unroll
     for (int ww = 1; ww < BLOCK / 64; ++ww) {
-      lo[d] = min(lo[d], red[ww * 6 + d]);
-      hi[d] = max(hi[d], red[ww * 6 + 3 + d]);
+      lo[d] = min(lo[d], red[ww * 7 + d]);
+      hi[d] = max(hi[d], red[ww * 7 + 3 + d]);
     }
   }
+  x = red[6];
+#pragma unroll
+  for (int ww = 1; ww < BLOCK / 64; ++ww) x = max(x, red[ww * 7 + 6]);
 }
 
 // q = x / d for 0 <= x < 2^23 with a float reciprocal and one correction
@@ -147,8 +153,8 @@ __device__ __forceinline__ void block_sum3(int v[3], int *red) {
 // A particle deposits into the block's LDS tile when its whole stencil (cell
 // -1 ... cell +2 in every dimension, in the tile's unwrapped frame) lies
 // inside it, else straight into the global current.
-template <int DIM, class Real>
-__device__ __forceinline__ bool in_tile(const DepTarget<Real> &tile, const int ts[3],
+template <int DIM, class Acc>
+__device__ __forceinline__ bool in_tile(const DepTarget<Acc> &tile, const int ts[3],
                                         const int ib[3]) {
   bool in = true;
 #pragma unroll
@@ -156,12 +162,20 @@ __device__ __forceinline__ bool in_tile(const DepTarget<Real> &tile, const int t
   return in;
 }
 
+// coefficient of a deposit into the tile: scaled by 2^esc for the
+// fixed-point accumulator of FP32 builds (exact power-of-two scaling)
+__device__ __forceinline__ float tile_coef(float C, int esc) { return ldexpf(C, esc); }
+__device__ __forceinline__ double tile_coef(double C, int) { return C; }
+
+template <class Real>
+using TileT = DepTarget<typename TileAcc<Real>::type>;
+
 template <int DIM, class Real>
 __device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s, int32_t c,
                                                  OffT<Real> q[3], Real u[3], Real w,
-                                                 const DepTarget<Real> &tile,
+                                                 const TileT<Real> &tile,
                                                  const DepTarget<Real> &glob, const int ts[3],
-                                                 const int shift[3]) {
+                                                 const int shift[3], int esc) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -208,10 +222,10 @@ __device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s,
     if (shift[a] && i[a] < (g.n[a] >> 1)) ib[a] += g.n[a];
   if (A.deposit) {
     const Real C = (Real)A.sp.qdt[s] * w;
-    if (in_tile<DIM, Real>(tile, ts, ib)) {
-      deposit<DIM, Real>(tile, C, ib, m, z, dx3);
+    if (in_tile<DIM>(tile, ts, ib)) {
+      deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3);
     } else {
-      deposit<DIM, Real>(glob, C, i, m, z, dx3);
+      deposit<DIM>(glob, C, i, m, z, dx3);
       if (A.stats) atomicAdd(A.stats + 1, 1);
     }
   }
@@ -268,8 +282,9 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
 template <int GEOM, class Real>
 __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int32_t c,
                                             OffT<Real> q[3], Real u[3], Real w, Real &phi,
-                                            const DepTarget<Real> &tile,
-                                            const DepTarget<Real> &glob, const int ts[3]) {
+                                            const TileT<Real> &tile,
+                                            const DepTarget<Real> &glob, const int ts[3],
+                                            int esc) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -320,10 +335,10 @@ __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int3
   zigzag<2, Real>(za, m, zb, z);
   if (A.deposit) {
     const Real C = (Real)A.sp.qdt[s] * w;
-    if (in_tile<2, Real>(tile, ts, i)) {
-      deposit<2, Real>(tile, C, i, m, z, dx3);
+    if (in_tile<2>(tile, ts, i)) {
+      deposit<2>(tile, tile_coef(C, esc), i, m, z, dx3);
     } else {
-      deposit<2, Real>(glob, C, i, m, z, dx3);
+      deposit<2>(glob, C, i, m, z, dx3);
       if (A.stats) atomicAdd(A.stats + 1, 1);
     }
   }
@@ -338,19 +353,19 @@ template <int GEOM, int DIM, class Real>
 __device__ __forceinline__ void push_particles(const StepArgs<Real> &A, int s, int cnt,
                                                int32_t cl[PPT], OffT<Real> qd[3][PPT],
                                                Real uu[3][PPT], const Real ww[PPT], Real ph[PPT],
-                                               const DepTarget<Real> &tile,
+                                               const TileT<Real> &tile,
                                                const DepTarget<Real> &glob, const int ts[3],
-                                               const int shift[3]) {
+                                               const int shift[3], int esc) {
   for (int r = 0; r < PPT; ++r) {
     if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
     OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
                        DIM > 2 ? qd[2][r] : (OffT<Real>)0};
     Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
     if (GEOM == 0) {
-      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tile, glob, ts, shift);
+      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tile, glob, ts, shift, esc);
     } else {
       Real p = ph[r];
-      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tile, glob, ts);
+      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tile, glob, ts, esc);
       ph[r] = p;
     }
 #pragma unroll
@@ -363,9 +378,10 @@ __device__ __forceinline__ void push_particles(const StepArgs<Real> &A, int s, i
 // ---------------------------------------------------------------- the kernel
 template <int GEOM, int DIM, class Real>
 __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
-  constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Real);
-  __shared__ Real tile[TILE_VALS];
-  __shared__ int red[6 * (BLOCK / 64)];
+  using Acc = typename TileAcc<Real>::type;
+  constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Acc);
+  __shared__ Acc tile[TILE_VALS];
+  __shared__ int red[7 * (BLOCK / 64)];
   const GridConst &g = A.g;
   int s;
   int64_t c0;
@@ -385,6 +401,14 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     for (int a = 0; a < DIM; ++a) store_n(A.prev_offs[a] + p0, cnt, qd[a]);
   }
 
+  Real ww[PPT];
+  load_n(A.p.w + p0, cnt, ww, (Real)0);
+  // largest |w| of the chunk (bit patterns of non-negative floats order like
+  // the values), for the fixed-point scale of the tile
+  int wbits = 0;
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) wbits = max(wbits, __float_as_int(fabsf((float)ww[r])));
+
   // bounding box of the chunk's current cells; a periodic dimension whose
   // cells span more than half the box is unwrapped (cells below N/2 shifted
   // by +N) so that a chunk straddling the boundary stays compact
@@ -400,7 +424,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
       hi[d] = max(hi[d], ic[r][d]);
     }
   }
-  block_minmax3(lo, hi, red);
+  block_minmax3(lo, hi, wbits, red);
   if (lo[0] > hi[0]) return;  // no live particle in the chunk (uniform)
   int shift[3] = {0, 0, 0};
   if (GEOM == 0) {
@@ -427,7 +451,8 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
           hi[d] = max(hi[d], v);
         }
       }
-      block_minmax3(lo, hi, red);
+      int unused = 0;
+      block_minmax3(lo, hi, unused, red);
     }
   }
   // tile placement: the whole box when it fits, else the largest cube (square
@@ -457,7 +482,8 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     block_sum3(sum, red);
     __syncthreads();
     block_sum3(nl, red);
-    constexpr int SIDE = (DIM == 3) ? ((sizeof(Real) == 4) ? 13 : 11) : ((sizeof(Real) == 4) ? 52 : 36);
+    static_assert(sizeof(Acc) == 8, "fallback tile sides assume 8-byte accumulators");
+    constexpr int SIDE = (DIM == 3) ? 11 : 36;  // 3 SIDE^DIM <= TILE_VALS
     T = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -468,15 +494,27 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     }
   }
 
-  Real uu[3][PPT], ww[PPT], ph[PPT];
+  Real uu[3][PPT], ph[PPT];
 #pragma unroll
   for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
-  load_n(A.p.w + p0, cnt, ww, (Real)0);
   if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
 
   const bool use_tile = A.deposit != 0;
   if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
-  DepTarget<Real> tile_t, glob_t;
+  // Fixed-point scale 2^esc: a particle adds at most B = |q dt/m| max|w| G to
+  // any tile value in one step (segment fluxes sum to under one cell, shape
+  // weights are at most 1; G bounds the out-of-plane factor: |dx3| < dt in 2D
+  // Cartesian, |dphi| <= pi in the axisymmetric geometries), so with
+  // B 2^esc < 2^49 one contribution stays below the 2^51 of fixed_round and
+  // the CHUNK particles of the block below 2^60.
+  int esc = 0;
+  if (sizeof(Acc) == 8 && sizeof(Real) == 4) {
+    const float G = (GEOM != 0) ? 4.0f : ((DIM == 2) ? 2.0f * fmaxf(1.0f, (float)A.dt) : 1.0f);
+    const float B = fabsf((float)A.sp.qdt[s]) * __int_as_float(wbits) * G;
+    if (B > 0.0f && B <= 3.0e38f) esc = 48 - ilogbf(B);
+  }
+  TileT<Real> tile_t;
+  DepTarget<Real> glob_t;
   tile_t.J = tile;
   tile_t.cs = (int)T;
   tile_t.sy = ts[0];
@@ -492,10 +530,10 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
   glob_t.o[1] = -NG;
   glob_t.o[2] = (DIM == 3) ? -NG : 0;
   if (use_tile) {
-    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Real)0;
+    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Acc)0;
     __syncthreads();
   }
-  push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tile_t, glob_t, ts, shift);
+  push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tile_t, glob_t, ts, shift, esc);
 
   store_n(A.p.cell + p0, cnt, cl);
 #pragma unroll
@@ -510,8 +548,9 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     const float iT = 1.0f / (float)Ti, i0f = 1.0f / (float)ts0, i01 = 1.0f / (float)ts01;
     const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
     for (int x = threadIdx.x; x < 3 * Ti; x += BLOCK) {
-      const Real v = tile[x];
-      if (v == (Real)0) continue;
+      const Acc acc = tile[x];
+      if (acc == (Acc)0) continue;
+      const Real v = (Real)ldexp((double)acc, -esc);
       const int comp = div_small(x, Ti, iT);
       int rem = x - comp * Ti;
       const int iz = div_small(rem, ts01, i01);

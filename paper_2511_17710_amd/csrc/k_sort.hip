@@ -3,8 +3,8 @@
 // Least-significant-digit radix sort on a cell key that orders cells brick by
 // brick (8-bit digits, dead particles carry the largest key), so equal keys
 // keep their previous order and the permutation is unique.  Per pass: tile histograms (digit-major
-// matrix), one exclusive scan of that matrix, and a stable in-tile ranking by
-// eight one-bit splits in LDS followed by a scatter.  A gather then reorders
+// matrix), one exclusive scan of that matrix, and a stable in-tile ranking
+// with wave ballots followed by a scatter.  A gather then reorders
 // every SoA array into the second particle set.
 #include "internal.h"
 
@@ -135,83 +135,102 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_add(int32_t *__restrict__
   }
 }
 
-// stable scatter of one tile: 8 one-bit splits in LDS rank the keys by digit
+// Stable scatter of one tile.  Wave w ranks the keys [w*1024, (w+1)*1024) of
+// the tile in 16 rounds of 64 consecutive keys: eight ballots find the lanes
+// holding the same digit, a lane's rank is the count of those peers below it
+// plus the wave's running count of the digit (a wave-private LDS counter
+// advanced by the lowest peer).  Rounds run in key order and waves are
+// ordered by their per-digit prefix, so equal digits keep their order.  The
+// tile is then staged in digit order in LDS and written out with consecutive
+// threads on consecutive destinations.
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
     int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ hist,
     int64_t ntiles) {
+  constexpr int NW = SORT_THREADS / 64;
+  constexpr int PER_WAVE = SORT_TILE / NW;
+  constexpr int ROUNDS = PER_WAVE / 64;
   __shared__ uint32_t sk[SORT_TILE];
   __shared__ int32_t sv[SORT_TILE];
+  __shared__ int cnt[NW][RADIX];
   __shared__ int dstart[RADIX];
-  __shared__ int goff[RADIX];
-  __shared__ int sw[SORT_THREADS / 64];
+  __shared__ int sw[NW];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
   const int nvalid = (int)min((int64_t)SORT_TILE, n - t0);
-  // coalesced load; padding keys carry the largest digit and sit at the end
+#pragma unroll
+  for (int ww = 0; ww < NW; ++ww) cnt[ww][threadIdx.x] = 0;
+  const int goff = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  __syncthreads();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t k[ROUNDS];
+  int32_t v[ROUNDS];
+  int rk[ROUNDS];
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const int e = w * PER_WAVE + j * 64 + lane;
+    const bool ok = e < nvalid;
+    k[j] = ok ? kin[t0 + e] : 0u;
+    v[j] = ok ? vin[t0 + e] : -1;
+    const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool set = (dg >> b) & 1u;
+      const uint64_t bb = __ballot(set);
+      peers &= set ? bb : ~bb;
+    }
+    const int r = __popcll(peers & below);
+    int base = 0;
+    if (ok) base = cnt[w][dg];
+    rk[j] = base + r;
+    if (ok && r == 0) cnt[w][dg] = base + __popcll(peers);
+  }
+  __syncthreads();
+  // per digit (one per thread): tile start and the waves' prefixes
+  {
+    const int d = threadIdx.x;
+    int c[NW], tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      c[ww] = cnt[ww][d];
+      tot += c[ww];
+    }
+    int all;
+    const int st = block_exclusive_scan(tot, &all, sw);
+    dstart[d] = st;
+    int run = st;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      cnt[ww][d] = run;
+      run += c[ww];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const int e = w * PER_WAVE + j * 64 + lane;
+    if (e < nvalid) {
+      const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
+      const int lp = cnt[w][dg] + rk[j];
+      sk[lp] = k[j];
+      sv[lp] = v[j];
+    }
+  }
+  __syncthreads();
+  // digit start of the tile in the global order, per digit
+  cnt[0][threadIdx.x] = goff;
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < SORT_ITEMS; ++j) {
     const int e = j * SORT_THREADS + threadIdx.x;
     if (e < nvalid) {
-      sk[e] = kin[t0 + e];
-      sv[e] = vin[t0 + e];
-    } else {
-      sk[e] = 0xffffffffu;
-      sv[e] = -1;
-    }
-  }
-  dstart[threadIdx.x] = 0;
-  goff[threadIdx.x] = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
-  __syncthreads();
-  uint32_t k[SORT_ITEMS];
-  int32_t v[SORT_ITEMS];
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    k[j] = sk[threadIdx.x * SORT_ITEMS + j];
-    v[j] = sv[threadIdx.x * SORT_ITEMS + j];
-  }
-  __syncthreads();
-  for (int b = 0; b < 8; ++b) {
-    const int bit = shift + b;
-    int zeros = 0;
-#pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) zeros += ((k[j] >> bit) & 1u) ? 0 : 1;
-    int ztot;
-    const int zpre = block_exclusive_scan(zeros, &ztot, sw);
-    int zc = zpre;
-    int oc = ztot + threadIdx.x * SORT_ITEMS - zpre;
-#pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) {
-      const int pos = ((k[j] >> bit) & 1u) ? oc++ : zc++;
-      sk[pos] = k[j];
-      sv[pos] = v[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < SORT_ITEMS; ++j) {
-      k[j] = sk[threadIdx.x * SORT_ITEMS + j];
-      v[j] = sv[threadIdx.x * SORT_ITEMS + j];
-    }
-    __syncthreads();
-  }
-  // first sorted position of every digit in this tile
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int spos = threadIdx.x * SORT_ITEMS + j;
-    if (spos < nvalid) {
-      const int dg = (k[j] >> shift) & (RADIX - 1);
-      const bool first = (spos == 0) || (((sk[spos - 1] >> shift) & (RADIX - 1)) != (uint32_t)dg);
-      if (first) dstart[dg] = spos;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int spos = threadIdx.x * SORT_ITEMS + j;
-    if (spos < nvalid) {
-      const int dg = (k[j] >> shift) & (RADIX - 1);
-      const int64_t dst = (int64_t)goff[dg] + (spos - dstart[dg]);
-      kout[dst] = k[j];
-      vout[dst] = v[j];
+      const uint32_t key = sk[e];
+      const uint32_t dg = (key >> shift) & (RADIX - 1);
+      const int64_t dst = (int64_t)cnt[0][dg] + (e - dstart[dg]);
+      kout[dst] = key;
+      vout[dst] = sv[e];
     }
   }
 }

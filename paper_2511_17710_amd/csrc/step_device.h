@@ -232,20 +232,42 @@ __device__ __forceinline__ void zigzag(const double a[3], const int m[3], const 
 __device__ __forceinline__ void atomic_add_r(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_r(double *p, double v) { unsafeAtomicAdd(p, v); }
 
+// LDS accumulator of a block's current tile.  FP32 builds accumulate in
+// 64-bit fixed point: every contribution is computed in float from a
+// coefficient pre-scaled by a power of two (so the float rounding is the
+// unscaled one), rounded to an integer and added with an integer LDS atomic.
+// The integer sum is exact and independent of the order of the adds, and on
+// gfx950 integer LDS atomics run several times faster than float ones.  FP64
+// builds accumulate in double.
+template <class Real>
+struct TileAcc { using type = Real; };
+template <>
+struct TileAcc<float> { using type = long long; };
+
+// round-to-nearest of a float v with |v| < 2^51: adding 1.5 * 2^52 in double
+// puts round(v) in the low mantissa bits of a number whose exponent is fixed
+__device__ __forceinline__ long long fixed_round(float v) {
+  const double d = (double)v + 0x1.8p52;
+  return __double_as_longlong(d) - 0x4338000000000000LL;
+}
+__device__ __forceinline__ void atomic_add_r(long long *p, float v) {
+  atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)fixed_round(v));
+}
+
 // Where a deposit lands: the global current (padded layout) or a block's LDS
 // tile; element (I, J, K) of component c sits at
 // c*cs + (I - o0) + sy*(J - o1) + sz*(K - o2).
-template <class Real>
+template <class Acc>
 struct DepTarget {
-  Real *J;
+  Acc *J;
   int cs, sy, sz;
   int o[3];
 };
 
 // Scatter of the two zig-zag segments (indices may reach the ghost layer of
 // the global array; periodic ghosts are folded after the step).
-template <int DIM, class Real>
-__device__ __forceinline__ void deposit(const DepTarget<Real> &t, Real C, const int i0[3],
+template <int DIM, class Real, class Acc>
+__device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const int i0[3],
                                         const int m[3], const ZigZag<Real> &z, Real dx3) {
   const int cs = t.cs, sy = t.sy, sz = t.sz;
 #pragma unroll
@@ -264,7 +286,7 @@ __device__ __forceinline__ void deposit(const DepTarget<Real> &t, Real C, const 
       atomic_add_r(t.J + cs + base + 1, cy * Wx);
       const Real h = C * dx3 * (Real)0.5;
       const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
-      Real *J3 = t.J + 2 * cs + base;
+      Acc *J3 = t.J + 2 * cs + base;
       atomic_add_r(J3, h * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy));
       atomic_add_r(J3 + 1, h * (Wx * ((Real)1 - Wy) - cxy));
       atomic_add_r(J3 + sy, h * (((Real)1 - Wx) * Wy - cxy));
@@ -276,17 +298,17 @@ __device__ __forceinline__ void deposit(const DepTarget<Real> &t, Real C, const 
       const Real cxz = Fx * Fz * (Real)(1.0 / 12.0);
       const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
       const Real gx = (Real)1 - Wx, gy = (Real)1 - Wy, gz = (Real)1 - Wz;
-      Real *J1 = t.J + base;
+      Acc *J1 = t.J + base;
       atomic_add_r(J1, cx * (gy * gz + cyz));
       atomic_add_r(J1 + sy, cx * (Wy * gz - cyz));
       atomic_add_r(J1 + sz, cx * (gy * Wz - cyz));
       atomic_add_r(J1 + sz + sy, cx * (Wy * Wz + cyz));
-      Real *J2 = t.J + cs + base;
+      Acc *J2 = t.J + cs + base;
       atomic_add_r(J2, cy * (gx * gz + cxz));
       atomic_add_r(J2 + 1, cy * (Wx * gz - cxz));
       atomic_add_r(J2 + sz, cy * (gx * Wz - cxz));
       atomic_add_r(J2 + sz + 1, cy * (Wx * Wz + cxz));
-      Real *J3 = t.J + 2 * cs + base;
+      Acc *J3 = t.J + 2 * cs + base;
       atomic_add_r(J3, cz * (gx * gy + cxy));
       atomic_add_r(J3 + 1, cz * (Wx * gy - cxy));
       atomic_add_r(J3 + sy, cz * (gx * Wy - cxy));

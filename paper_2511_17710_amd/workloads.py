@@ -288,10 +288,15 @@ def cart2d(n=64, ppc=8, theta=0.1, steps=10, seed=None, index=1, shuffle=False):
 
 
 def cart3d(n=128, ppc=16, theta=1.0, drift=0.3, steps=100, nwaves=32, amp=0.05, seed=None,
-           index=2, name=None, shuffle=False):
+           index=2, name=None, shuffle=False, sort_every=4):
+    """3D periodic pair plasma.  The sort cadence of 4 steps keeps every
+    1024-particle chunk of a brick within the LDS current tile of the push
+    kernel: at CFL 0.45 and theta = 1 the chunk's bounding box grows by about
+    one cell per step, and past a side of 11 cells its particles spill to
+    global atomics."""
     rp, ru, rf, rw, rW = _streams(index, seed)
     wl = Workload(name=name or f"cart3d_{n}", geom="cart", dim=3, n=(n, n, n),
-                  lo=(0.0, 0.0, 0.0), hi=(float(n),) * 3, steps=steps, sort_every=20,
+                  lo=(0.0, 0.0, 0.0), hi=(float(n),) * 3, steps=steps, sort_every=sort_every,
                   seed=index)
     cell, offs = _load_uniform(rp, wl, ppc, (n, n, n))
     N = cell.shape[0]
