@@ -81,8 +81,8 @@ __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int
   return c0 < sp.n[s];
 }
 
-// block-wide min/max of three ints and max of a fourth (256 threads)
-__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int &x, int *red) {
+// block-wide min/max of three ints (256 threads)
+__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -91,16 +91,13 @@ __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int &x, int 
       hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
     }
   }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      red[w * 7 + d] = lo[d];
-      red[w * 7 + 3 + d] = hi[d];
+      red[w * 6 + d] = lo[d];
+      red[w * 6 + 3 + d] = hi[d];
     }
-    red[w * 7 + 6] = x;
   }
   __syncthreads();
 #pragma unroll
@@ -109,13 +106,24 @@ __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int &x, int 
     hi[d] = red[3 + d];
 #pragma unroll
     for (int ww = 1; ww < BLOCK / 64; ++ww) {
-      lo[d] = min(lo[d], red[ww * 7 + d]);
-      hi[d] = max(hi[d], red[ww * 7 + 3 + d]);
+      lo[d] = min(lo[d], red[ww * 6 + d]);
+      hi[d] = max(hi[d], red[ww * 6 + 3 + d]);
     }
   }
-  x = red[6];
+}
+
+// block-wide maximum of a non-negative float (its bit pattern orders like
+// the value)
+__device__ __forceinline__ float block_max_nonneg(float v, int *red) {
+  int x = __float_as_int(v);
 #pragma unroll
-  for (int ww = 1; ww < BLOCK / 64; ++ww) x = max(x, red[ww * 7 + 6]);
+  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  x = red[0];
+#pragma unroll
+  for (int ww = 1; ww < BLOCK / 64; ++ww) x = max(x, red[ww]);
+  return __int_as_float(x);
 }
 
 // q = x / d for 0 <= x < 2^23 with a float reciprocal and one correction
@@ -170,12 +178,20 @@ __device__ __forceinline__ double tile_coef(double C, int) { return C; }
 template <class Real>
 using TileT = DepTarget<typename TileAcc<Real>::type>;
 
+// Step m of every dimension packed two bits each (m + 1)
+__device__ __forceinline__ int pack_m(const int m[3]) {
+  return (m[0] + 1) | ((m[1] + 1) << 2) | ((m[2] + 1) << 4);
+}
+__device__ __forceinline__ void unpack_m(int p, int m[3]) {
+  m[0] = (p & 3) - 1;
+  m[1] = ((p >> 2) & 3) - 1;
+  m[2] = ((p >> 4) & 3) - 1;
+}
+
 template <int DIM, class Real>
-__device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s, int32_t c,
-                                                 OffT<Real> q[3], Real u[3], Real w,
-                                                 const TileT<Real> &tile,
-                                                 const DepTarget<Real> &glob, const int ts[3],
-                                                 const int shift[3], int esc) {
+__device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, int s, int32_t c,
+                                             OffT<Real> q[3], Real u[3], int &mp, Real &dx3,
+                                             float &span) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -197,38 +213,20 @@ __device__ __forceinline__ int32_t cart_particle(const StepArgs<Real> &A, int s,
   const Real gi = rsqrt_r((Real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const Real dtr = (Real)A.dt;
   int m[3] = {0, 0, 0};
-  double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
   int inew[3] = {i[0], i[1], i[2]};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const Real dx = dtr * u[a] * gi / (Real)g.dx[a];
     OffT<Real> qn;
     m[a] = PS::move(q[a], (double)dx, qn);
-    za[a] = PS::exact(q[a]);
-    zb[a] = PS::exact(qn) + (double)m[a];
+    span = fmaxf(span, (float)fabs(PS::exact(qn) + (double)m[a] - PS::exact(q[a])));
     q[a] = qn;
     int v = i[a] + m[a];
     v = (v < 0) ? v + g.n[a] : ((v >= g.n[a]) ? v - g.n[a] : v);  // periodic wrap
     inew[a] = v;
   }
-  const Real dx3 = (DIM == 2) ? dtr * u[2] * gi : (Real)0;
-  // deposit (step 8) with the unwrapped step m; periodic ghosts are folded
-  // later, a tile uses the image of the cell that keeps the box compact
-  ZigZag<Real> z;
-  zigzag<DIM, Real>(za, m, zb, z);
-  int ib[3] = {i[0], i[1], i[2]};
-#pragma unroll
-  for (int a = 0; a < DIM; ++a)
-    if (shift[a] && i[a] < (g.n[a] >> 1)) ib[a] += g.n[a];
-  if (A.deposit) {
-    const Real C = (Real)A.sp.qdt[s] * w;
-    if (in_tile<DIM>(tile, ts, ib)) {
-      deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3);
-    } else {
-      deposit<DIM>(glob, C, i, m, z, dx3);
-      if (A.stats) atomicAdd(A.stats + 1, 1);
-    }
-  }
+  dx3 = (DIM == 2) ? dtr * u[2] * gi : (Real)0;
+  mp = pack_m(m);
   return cell_encode(g, inew);
 }
 
@@ -280,11 +278,9 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
 }
 
 template <int GEOM, class Real>
-__device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int32_t c,
-                                            OffT<Real> q[3], Real u[3], Real w, Real &phi,
-                                            const TileT<Real> &tile,
-                                            const DepTarget<Real> &glob, const int ts[3],
-                                            int esc) {
+__device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, int s, int32_t c,
+                                            OffT<Real> q[3], Real u[3], Real &phi, int &mp,
+                                            Real &dx3, float &span) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -297,7 +293,7 @@ __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int3
   interp6<2, Real>(A.EB, g, st, F);
   const Real k = (Real)A.sp.k[s];
   double dx1, dx2;
-  Real phinew, dx3;
+  Real phinew;
   const bool near = (i[0] < g.fp64_cells) || (i[1] < g.fp64_cells) ||
                     (i[1] >= g.n[1] - g.fp64_cells);
   if (sizeof(Real) == 8 || near) {
@@ -329,49 +325,50 @@ __device__ __forceinline__ int32_t axi_step(const StepArgs<Real> &A, int s, int3
   }
   m[1] = inew[1] - i[1];
   const bool alive = inew[0] >= 0 && inew[0] < g.n[0];  // radial exit
-  const double za[3] = {PS::exact(q[0]), PS::exact(q[1]), 0.0};
-  const double zb[3] = {PS::exact(qn1) + (double)m[0], PS::exact(qn2) + (double)m[1], 0.0};
-  ZigZag<Real> z;
-  zigzag<2, Real>(za, m, zb, z);
-  if (A.deposit) {
-    const Real C = (Real)A.sp.qdt[s] * w;
-    if (in_tile<2>(tile, ts, i)) {
-      deposit<2>(tile, tile_coef(C, esc), i, m, z, dx3);
-    } else {
-      deposit<2>(glob, C, i, m, z, dx3);
-      if (A.stats) atomicAdd(A.stats + 1, 1);
-    }
-  }
+  span = fmaxf(span, (float)fabs(PS::exact(qn1) + (double)m[0] - PS::exact(q[0])));
+  span = fmaxf(span, (float)fabs(PS::exact(qn2) + (double)m[1] - PS::exact(q[1])));
   q[0] = qn1;
   q[1] = qn2;
   phi = phinew;
+  mp = pack_m(m);
   return cell_encode(g, inew) | (alive ? 0 : DEAD_BIT);
 }
 
-// the block's particles one after the other (each thread: up to PPT)
+// Deposit (step 8) of one pushed particle from its old and new positions:
+// zig-zag with the unwrapped step m; periodic ghosts are folded after the
+// step, and a tile uses the image of the old cell that keeps the box compact.
 template <int GEOM, int DIM, class Real>
-__device__ __forceinline__ void push_particles(const StepArgs<Real> &A, int s, int cnt,
-                                               int32_t cl[PPT], OffT<Real> qd[3][PPT],
-                                               Real uu[3][PPT], const Real ww[PPT], Real ph[PPT],
-                                               const TileT<Real> &tile,
-                                               const DepTarget<Real> &glob, const int ts[3],
-                                               const int shift[3], int esc) {
-  for (int r = 0; r < PPT; ++r) {
-    if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
-    OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
-                       DIM > 2 ? qd[2][r] : (OffT<Real>)0};
-    Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
-    if (GEOM == 0) {
-      cl[r] = cart_particle<DIM, Real>(A, s, cl[r], q, u, ww[r], tile, glob, ts, shift, esc);
-    } else {
-      Real p = ph[r];
-      cl[r] = axi_step<GEOM, Real>(A, s, cl[r], q, u, ww[r], p, tile, glob, ts, esc);
-      ph[r] = p;
-    }
+__device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s, int32_t c_old,
+                                                 const OffT<Real> qo[3], const OffT<Real> qn[3],
+                                                 int mp, Real w, Real dx3,
+                                                 const TileT<Real> &tile,
+                                                 const DepTarget<Real> &glob, const int ts[3],
+                                                 const int shift[3], int esc) {
+  using PS = Pos<Real>;
+  const GridConst &g = A.g;
+  int i[3], m[3];
+  cell_decode(g, c_old, i);
+  unpack_m(mp, m);
+  double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
+  for (int a = 0; a < DIM; ++a) {
+    za[a] = PS::exact(qo[a]);
+    zb[a] = PS::exact(qn[a]) + (double)m[a];
+  }
+  ZigZag<Real> z;
+  zigzag<DIM, Real>(za, m, zb, z);
+  int ib[3] = {i[0], i[1], i[2]};
+  if (GEOM == 0) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
+    for (int a = 0; a < DIM; ++a)
+      if (shift[a] && i[a] < (g.n[a] >> 1)) ib[a] += g.n[a];
+  }
+  const Real C = (Real)A.sp.qdt[s] * w;
+  if (in_tile<DIM>(tile, ts, ib)) {
+    deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3);
+  } else {
+    deposit<DIM>(glob, C, i, m, z, dx3);
+    if (A.stats) atomicAdd(A.stats + 1, 1);
   }
 }
 
@@ -381,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
   using Acc = typename TileAcc<Real>::type;
   constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Acc);
   __shared__ Acc tile[TILE_VALS];
-  __shared__ int red[7 * (BLOCK / 64)];
+  __shared__ int red[6 * (BLOCK / 64)];
   const GridConst &g = A.g;
   int s;
   int64_t c0;
@@ -401,14 +398,6 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     for (int a = 0; a < DIM; ++a) store_n(A.prev_offs[a] + p0, cnt, qd[a]);
   }
 
-  Real ww[PPT];
-  load_n(A.p.w + p0, cnt, ww, (Real)0);
-  // largest |w| of the chunk (bit patterns of non-negative floats order like
-  // the values), for the fixed-point scale of the tile
-  int wbits = 0;
-#pragma unroll
-  for (int r = 0; r < PPT; ++r) wbits = max(wbits, __float_as_int(fabsf((float)ww[r])));
-
   // bounding box of the chunk's current cells; a periodic dimension whose
   // cells span more than half the box is unwrapped (cells below N/2 shifted
   // by +N) so that a chunk straddling the boundary stays compact
@@ -424,7 +413,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
       hi[d] = max(hi[d], ic[r][d]);
     }
   }
-  block_minmax3(lo, hi, wbits, red);
+  block_minmax3(lo, hi, red);
   if (lo[0] > hi[0]) return;  // no live particle in the chunk (uniform)
   int shift[3] = {0, 0, 0};
   if (GEOM == 0) {
@@ -451,8 +440,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
           hi[d] = max(hi[d], v);
         }
       }
-      int unused = 0;
-      block_minmax3(lo, hi, unused, red);
+      block_minmax3(lo, hi, red);
     }
   }
   // tile placement: the whole box when it fits, else the largest cube (square
@@ -494,24 +482,75 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     }
   }
 
-  Real uu[3][PPT], ph[PPT];
+  Real uu[3][PPT], ww[PPT], ph[PPT];
 #pragma unroll
   for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
+  load_n(A.p.w + p0, cnt, ww, (Real)0);
   if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
 
   const bool use_tile = A.deposit != 0;
   if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
-  // Fixed-point scale 2^esc: a particle adds at most B = |q dt/m| max|w| G to
-  // any tile value in one step (segment fluxes sum to under one cell, shape
-  // weights are at most 1; G bounds the out-of-plane factor: |dx3| < dt in 2D
-  // Cartesian, |dphi| <= pi in the axisymmetric geometries), so with
-  // B 2^esc < 2^49 one contribution stays below the 2^51 of fixed_round and
-  // the CHUNK particles of the block below 2^60.
+  if (use_tile)
+    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Acc)0;
+
+  // pass 1: interpolate, rotate, push and move every particle of the thread
+  // (steps 3-7), keeping the old position for the deposit
+  int32_t co[PPT];
+  OffT<Real> qo[3][PPT];
+  int mp[PPT];
+  Real d3[PPT];
+  float bmax = 0.0f;
+  const Real qdt = (Real)A.sp.qdt[s];
+#pragma unroll
+  for (int r = 0; r < PPT; ++r) {
+    co[r] = cl[r];
+    mp[r] = 0;
+    d3[r] = (Real)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) qo[a][r] = qd[a][r];
+    if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
+    OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
+                       DIM > 2 ? qd[2][r] : (OffT<Real>)0};
+    Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
+    float span = 0.0f;
+    Real dx3;
+    if (GEOM == 0) {
+      cl[r] = cart_push<DIM, Real>(A, s, cl[r], q, u, mp[r], dx3, span);
+    } else {
+      Real p = ph[r];
+      cl[r] = axi_push<GEOM, Real>(A, s, cl[r], q, u, p, mp[r], dx3, span);
+      ph[r] = p;
+    }
+    d3[r] = dx3;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
+    bmax = fmaxf(bmax, fabsf((float)(qdt * ww[r])) * fmaxf(span, fabsf((float)dx3)));
+  }
+
+  store_n(A.p.cell + p0, cnt, cl);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
+  if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+  if (!use_tile) return;  // uniform
+
+  // Fixed-point scale 2^esc of the FP32 tile from the block's largest
+  // contribution bound: one particle adds at most B = |q w dt/m| max(span,
+  // |dx3|) to any tile value (its segment fluxes along a dimension sum to
+  // its displacement there, span the largest; shape weights are at most 1;
+  // the out-of-plane current of 2D grids carries dx3).  With B 2^esc < 2^49
+  // one contribution stays below the 2^51 of fixed_round and the CHUNK
+  // particles of the block below 2^60, and small displacements (cold plasma)
+  // keep the full 48-bit resolution relative to the largest of the block.
   int esc = 0;
   if (sizeof(Acc) == 8 && sizeof(Real) == 4) {
-    const float G = (GEOM != 0) ? 4.0f : ((DIM == 2) ? 2.0f * fmaxf(1.0f, (float)A.dt) : 1.0f);
-    const float B = fabsf((float)A.sp.qdt[s]) * __int_as_float(wbits) * G;
+    const float B = block_max_nonneg(bmax, red);  // also orders the tile zeroing
     if (B > 0.0f && B <= 3.0e38f) esc = 48 - ilogbf(B);
+  } else {
+    __syncthreads();  // tile zeroed
   }
   TileT<Real> tile_t;
   DepTarget<Real> glob_t;
@@ -529,18 +568,18 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
   glob_t.o[0] = -NG;
   glob_t.o[1] = -NG;
   glob_t.o[2] = (DIM == 3) ? -NG : 0;
-  if (use_tile) {
-    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Acc)0;
-    __syncthreads();
-  }
-  push_particles<GEOM, DIM, Real>(A, s, cnt, cl, qd, uu, ww, ph, tile_t, glob_t, ts, shift, esc);
 
-  store_n(A.p.cell + p0, cnt, cl);
+  // pass 2: deposit (step 8)
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
-  if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+  for (int r = 0; r < PPT; ++r) {
+    if (r >= cnt || (co[r] & DEAD_BIT)) continue;
+    OffT<Real> a0[3] = {qo[0][r], DIM > 1 ? qo[1][r] : (OffT<Real>)0,
+                        DIM > 2 ? qo[2][r] : (OffT<Real>)0};
+    OffT<Real> a1[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
+                        DIM > 2 ? qd[2][r] : (OffT<Real>)0};
+    deposit_particle<GEOM, DIM, Real>(A, s, co[r], a0, a1, mp[r], ww[r], d3[r], tile_t, glob_t,
+                                      ts, shift, esc);
+  }
 
   if (use_tile) {
     __syncthreads();

@@ -25,11 +25,16 @@ def oracle_fields(wl, prec):
     return g, EB
 
 
-def kick_scale(wl, g, EB, dt):
-    """|k E_p| per particle of every species at the initial state (reference)."""
+def kick_scale(wl, g, EB, dt, stencil=False):
+    """|k E_p| per particle of every species at the initial state (reference).
+
+    stencil=True interpolates |E| instead: |k| times the norm of
+    sqrt(h_ii) sum_nodes w |E^i|, the scale of the rounding error of the
+    interpolation sum (where E nearly vanishes at the particle, e.g. next to
+    the polar axis, the stored node values set the error, not their sum)."""
     out = []
     for s in wl.species:
-        F = O.interp(g, EB, s["cell"], s["offs"])
+        F = O.interp(g, np.abs(EB) if stencil else EB, s["cell"], s["offs"])
         E, _ = O.to_cart(g, s["cell"], s["offs"], s.get("phi"), F)
         k = s["q"] * dt / (2 * s["m"] * wl.rho0)
         out.append(np.abs(k) * np.linalg.norm(E, axis=1))
