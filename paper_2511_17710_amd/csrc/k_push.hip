@@ -71,8 +71,20 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 }
 
 // ---------------------------------------------------------------- block -> chunk
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  Block b = 8k + x is given the k-th
+// chunk of XCD x's contiguous share of the chunk sequence, so that one XCD
+// works through neighbouring chunks (neighbouring cells after the sort) and
+// its L2 holds the fields and current around them.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblk) {
+  const int64_t q = nblk / NXCD, r = nblk % NXCD;
+  const int64_t x = b % NXCD, k = b / NXCD;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0) {
-  const int64_t b = blockIdx.x;
+  const int64_t b = xcd_chunk(blockIdx.x, sp.blk0[MAXSP]);  // blk0[MAXSP] = all blocks
   s = 0;
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
