@@ -36,6 +36,31 @@ def algorithmic_bytes_per_particle(dim, prec, ncells, nparticles, has_phi=False)
     return rd + wr + grid
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of the push kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None once the kernel's sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in kv["kernel_sources"].split():
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv["kernel_sources_sha256"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def run_gpu(wl, prec, steps, warmup, log):
     import torch
 
@@ -204,7 +229,10 @@ def main():
                    "species": len(wl.species), "sort_every": wl.sort_every, "cfl": wl.cfl,
                    "offsets": "u32 fixed point (f32 build)"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": (measured_traffic(f"k_push_{wl.name}")
+                                 if wl.name == "cart3d_128" else None),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": kname,
                      "bytes_per_particle": round(bpp32, 3),
                      "kernel_ms_avg": round(r32["push_ms_avg"], 4)},
