@@ -97,16 +97,16 @@ def run_gpu(wl, prec, steps, warmup, log):
 
 
 def run_adjoint(prec, log, name="cart3d_64_adj"):
-    """Checkpointed forward (K steps, state every m) and the hand-written
-    reverse sweep of L = sum(W * J_K) on the 3D Cartesian 64^3 workload."""
+    """Checkpointed forward (K steps, state every m, sorts at the workload's
+    cadence inside the map) and the hand-written reverse sweep of
+    L = sum(W * J_K) on the 3D Cartesian 64^3 workload."""
     import torch
 
     from paper_2511_17710_amd import picstep as P
     from paper_2511_17710_amd import workloads as W
     wl = W.by_name(name)
     K, m = wl.K, wl.ckpt_every
-    ctx = P.from_workload(wl, prec=prec, sort_every=0)
-    ctx.sort()  # cell order before the differentiated steps (not part of the map)
+    ctx = P.from_workload(wl, prec=prec)  # the workload's sort cadence, inside the map
     dt = ctx.timestep_from_cfl(wl.cfl)
     lamJ = torch.from_numpy(wl.W).to(device="cuda", dtype=ctx.dtype)
     ctx.forward_checkpointed(dt, 2, 1)  # warm-up
@@ -123,7 +123,7 @@ def run_adjoint(prec, log, name="cart3d_64_adj"):
     torch.cuda.synchronize()
     tm = ctx.timing_read()
     n = wl.nparticles
-    res = dict(workload=wl.name, particles=n, K=K, checkpoint_every=m,
+    res = dict(workload=wl.name, particles=n, K=K, checkpoint_every=m, sort_every=wl.sort_every,
                forward_ns_per_particle_step=e[0].elapsed_time(e[1]) * 1e6 / (n * K),
                backward_ns_per_particle_step=e[1].elapsed_time(e[2]) * 1e6 / (n * K),
                adjoint_kernel_ms_avg=tm["adjoint_ms"] / max(tm["adjoint_launches"], 1),

@@ -262,21 +262,36 @@ pic_status pic_timing_read(pic_ctx *ctx, pic_timing *out);
 /* Workspace bytes for pic_forward_checkpointed / pic_backward with K, m. */
 pic_status pic_adjoint_workspace(const pic_ctx *ctx, int32_t K, int32_t m, uint64_t *bytes);
 
-/* K steps without sorting, saving the state at steps 0, m, 2m, ... into
- * `workspace` (device, pic_adjoint_workspace bytes).  Leaves the context at
- * step K with J of the last step, like pic_push_deposit.  Asynchronous. */
+/* K steps exactly as pic_push_deposit(dt, K) runs them, sorts included (a
+ * sort before every step whose global index is a multiple of sort_every),
+ * saving the state (cell, offsets, u, w, phi) at steps 0, m, 2m, ... before
+ * that step's sort, and the permutation of every sort, into `workspace`
+ * (device, pic_adjoint_workspace bytes, which covers ceil(K / sort_every)
+ * sorts).  Leaves the context at step K with J of the last step, like
+ * pic_push_deposit.  Asynchronous. */
 pic_status pic_forward_checkpointed(pic_ctx *ctx, double dt, int32_t K, int32_t m,
                                     void *workspace);
 
 /* Reverse sweep after pic_forward_checkpointed(dt, K, m, workspace).
  * lamJ: device [3][npts] real (dL/dJ_K; may be NULL = 0); lam_u: device
- * [3][capacity] real in the particle order of the checkpoints (may be NULL).
+ * [3][capacity] real in the particle order at step K (may be NULL).
  * Outputs (device, overwritten): dEB [6][npts] real, dL/d(fields) with
  * periodic ghost contributions added into their images (ghosts 0);
- * du0 [3][capacity] real, dL/du at step 0.  Restores the particle state of
- * step 0.  Asynchronous. */
+ * du0 [3][capacity] real, dL/du at step 0 in the particle order at step 0
+ * (before that step's sort).  Segments are recomputed from the checkpoints
+ * replaying the stored permutations, and the adjoints of the particles
+ * follow every sort backwards.  Restores the particle state of step 0.
+ * Asynchronous. */
 pic_status pic_backward(pic_ctx *ctx, double dt, int32_t K, int32_t m, void *workspace,
                         const void *lamJ, const void *lam_u, void *dEB, void *du0);
+
+/* After pic_forward_checkpointed(..., workspace): for every particle slot i
+ * (0 <= i < capacity, species ranges as in pic_particle_layout) of the order
+ * at step K, the slot the same particle had at step 0, composed from the
+ * stored sort permutations (identity outside the species' counts).  dst:
+ * host int32[capacity].  Synchronizes the bound stream.  PIC_E_STATE without
+ * a completed forward. */
+pic_status pic_checkpointed_order(const pic_ctx *ctx, const void *workspace, int32_t *dst);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);

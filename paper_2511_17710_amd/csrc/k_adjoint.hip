@@ -5,9 +5,12 @@
 // and the interpolation (a scatter into dL/dE, dL/dB).  Discrete branches
 // (cell crossings, the relay clamp, the half-cell stagger choice) take the
 // derivative of the branch the forward step took.
+#include "block_util.h"
 #include "step_device.h"
 
 namespace picstep {
+
+constexpr int ADJ_TILE_BYTES = 32768;  // LDS tile of dL/d(fields) per block
 
 // forward interpolation of one component that also returns the corner values
 template <int DIM, class Real>
@@ -23,18 +26,94 @@ __device__ __forceinline__ void corners(const Real *__restrict__ A, const GridCo
   }
 }
 
+// One particle per thread, BLOCK particles per block in XCD-aware order.  The
+// scatter into dL/dE, dL/dB (the adjoint of the interpolation) goes to an LDS
+// tile over the block's cells, accumulated like the forward current (64-bit
+// fixed point in FP32 builds, scaled by the block's largest |dL/dF|) and
+// flushed with one global atomic per nonzero value; particles whose stencil
+// leaves the tile scatter with global atomics.
 template <int DIM, class Real>
 __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   using PS = Pos<Real>;
-  int s;
-  int64_t local;
-  if (!locate(A.sp, s, local)) return;
-  const int64_t p = A.sp.off[s] + local;
+  using Acc = typename TileAcc<Real>::type;
+  constexpr int TILE_VALS = ADJ_TILE_BYTES / (int)sizeof(Acc);
+  __shared__ Acc tile[TILE_VALS];
+  __shared__ int red[6 * (BLOCK / 64)];
   const GridConst &g = A.g;
-  const int32_t cc = A.p.cell[p];
-  if (cc & DEAD_BIT) return;  // frozen particle: identity map, adjoints pass through
+  const int64_t blk = xcd_chunk(blockIdx.x, A.sp.blk0[MAXSP]);  // blk0[MAXSP] = all blocks
+  int s = 0;
+#pragma unroll
+  for (int t = 1; t < MAXSP; ++t)
+    if (t < A.sp.nspec && blk >= A.sp.blk0[t]) s = t;
+  const int64_t local = (blk - A.sp.blk0[s]) * BLOCK + threadIdx.x;
+  const bool inrange = local < A.sp.n[s];
+  const int64_t p = A.sp.off[s] + (inrange ? local : 0);
+  const int32_t cc = inrange ? A.p.cell[p] : (int32_t)DEAD_BIT;
+  // a frozen (dead) particle maps to itself: its adjoints pass through
+  const bool live = !(cc & DEAD_BIT);
   int i[3];
   cell_decode(g, cc, i);
+
+  // ---------------- the block's box and its LDS tile (stencils reach i-1 .. i+1)
+  int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  if (live) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = i[d];
+  }
+  block_minmax3(lo, hi, red);
+  if (lo[0] > hi[0]) return;  // no live particle in the block (uniform)
+  int shift[3] = {0, 0, 0}, ib[3] = {i[0], i[1], i[2]};
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    shift[d] = (hi[d] - lo[d] > (g.n[d] >> 1)) ? 1 : 0;
+    any = any || shift[d];
+    if (shift[d] && ib[d] < (g.n[d] >> 1)) ib[d] += g.n[d];
+  }
+  if (any) {  // a block straddling a periodic boundary: box of the unwrapped cells
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = live ? ib[d] : INT32_MAX;
+      hi[d] = live ? ib[d] : INT32_MIN;
+    }
+    block_minmax3(lo, hi, red);
+  }
+  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1};
+  int T = 1;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    ts[d] = hi[d] - lo[d] + 3;
+    T *= ts[d];
+  }
+  if (6 * T <= TILE_VALS) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) t0[d] = lo[d] - 1;
+  } else {  // largest cube (square) centred on the block's mean cell
+    __syncthreads();
+    int sum[3] = {0, 0, 0}, nl[3] = {live ? 1 : 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) sum[d] = live ? ib[d] : 0;
+    block_sum3(sum, red);
+    __syncthreads();
+    block_sum3(nl, red);
+    static_assert(sizeof(Acc) == 8, "fallback tile sides assume 8-byte accumulators");
+    constexpr int SIDE = (DIM == 3) ? 8 : 26;  // 6 SIDE^DIM <= TILE_VALS
+    T = 1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int ctr = (sum[d] + nl[0] / 2) / nl[0];
+      ts[d] = SIDE;
+      t0[d] = ctr - SIDE / 2;
+      T *= ts[d];
+    }
+  }
+  for (int x = threadIdx.x; x < 6 * T; x += BLOCK) tile[x] = (Acc)0;
+
+  Real Fbar[6] = {0, 0, 0, 0, 0, 0};
+  Stencil1<Real> st[3];
+  float bmax = 0.0f;
+  if (live) {
   OffT<Real> q[3];
   Real d[3] = {0, 0, 0};
 #pragma unroll
@@ -48,7 +127,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   const Real dtr = (Real)A.dt;
 
   // ---------------- forward recompute (step 3: interpolation, keeping corners)
-  Stencil1<Real> st[3];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], d[a]);
   Real F[6];
@@ -242,8 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     umb[a] += gmb * um[a] * igm;
     Eb[a] += k * umb[a];
   }
-  // tetrad reversed and interpolation reversed (scatter + offset derivative)
-  Real Fbar[6];
+  // tetrad reversed; the offset derivative of the interpolation
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     Fbar[a] = Eb[a] * sc[a];
@@ -263,23 +340,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     corners<DIM, Real>(A.EB + c * (int)g.npts, g, bx, by, bz, cv, ix);
     const Real gx = (Real)1 - fx, gy = (Real)1 - fy, gz = (Real)1 - fz;
     const Real fb = Fbar[c];
-    Real *dE = A.dEB + c * (int)g.npts;
+    bmax = fmaxf(bmax, fabsf((float)fb));
     if (DIM == 2) {
-      atomic_add_r(dE + ix[0], fb * gx * gy);
-      atomic_add_r(dE + ix[1], fb * fx * gy);
-      atomic_add_r(dE + ix[2], fb * gx * fy);
-      atomic_add_r(dE + ix[3], fb * fx * fy);
       ab[0] += fb * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]));
       ab[1] += fb * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]));
     } else {
-      atomic_add_r(dE + ix[0], fb * gx * gy * gz);
-      atomic_add_r(dE + ix[1], fb * fx * gy * gz);
-      atomic_add_r(dE + ix[2], fb * gx * fy * gz);
-      atomic_add_r(dE + ix[3], fb * fx * fy * gz);
-      atomic_add_r(dE + ix[4], fb * gx * gy * fz);
-      atomic_add_r(dE + ix[5], fb * fx * gy * fz);
-      atomic_add_r(dE + ix[6], fb * gx * fy * fz);
-      atomic_add_r(dE + ix[7], fb * fx * fy * fz);
       ab[0] += fb * (gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
                      fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6])));
       ab[1] += fb * (gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
@@ -292,6 +357,90 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   for (int a = 0; a < 3; ++a) A.lam_u[a][p] = umb[a];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
+  }  // live
+
+  // ---------------- scatter of dL/dF into the tile (or global memory)
+  // Fixed-point scale 2^esc (FP32): one particle adds at most max|dL/dF| to a
+  // tile value (interpolation weights are at most 1), so with B 2^esc < 2^49
+  // the BLOCK particles of the block stay below 2^57.
+  int esc = 0;
+  if (sizeof(Acc) == 8 && sizeof(Real) == 4) {
+    const float B = block_max_nonneg(bmax, red);  // also orders the tile zeroing
+    if (B > 0.0f && B <= 3.0e38f) esc = 48 - ilogbf(B);
+  } else {
+    __syncthreads();
+  }
+  if (live) {
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) in = in && (ib[d] - 1 >= t0[d]) && (ib[d] + 1 < t0[d] + ts[d]);
+    const int dsh[3] = {ib[0] - i[0], ib[1] - i[1], ib[2] - i[2]};
+    const int sy = ts[0], sz = ts[0] * ts[1];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
+      const int bx = sx ? st[0].bh : st[0].b0;
+      const int by = sy2 ? st[1].bh : st[1].b0;
+      const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
+      const Real fx = sx ? st[0].fh : st[0].f0;
+      const Real fy = sy2 ? st[1].fh : st[1].f0;
+      const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
+      const Real gx = (Real)1 - fx, gy = (Real)1 - fy, gz = (Real)1 - fz;
+      Real wt[8];
+      wt[0] = gx * gy;
+      wt[1] = fx * gy;
+      wt[2] = gx * fy;
+      wt[3] = fx * fy;
+      if (DIM == 3) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          wt[4 + e] = wt[e] * fz;
+          wt[e] *= gz;
+        }
+      }
+      if (in) {
+        const Real fb = tile_coef(Fbar[c], esc);
+        const int base = c * T + (bx + dsh[0] - t0[0]) + sy * (by + dsh[1] - t0[1]) +
+                         ((DIM == 3) ? sz * (bz + dsh[2] - t0[2]) : 0);
+#pragma unroll
+        for (int e = 0; e < (1 << DIM); ++e) {
+          const int o = (e & 1) + ((e >> 1) & 1) * sy + ((DIM == 3) ? ((e >> 2) & 1) * sz : 0);
+          atomic_add_r(tile + base + o, fb * wt[e]);
+        }
+      } else {
+        const Real fb = Fbar[c];
+        Real *dE = A.dEB + c * (int)g.npts;
+        const int np0 = g.np[0], np01 = np0 * g.np[1];
+        const int base = pad_index(g, bx, by, bz, DIM);
+#pragma unroll
+        for (int e = 0; e < (1 << DIM); ++e) {
+          const int o = (e & 1) + ((e >> 1) & 1) * np0 + ((DIM == 3) ? ((e >> 2) & 1) * np01 : 0);
+          atomic_add_r(dE + base + o, fb * wt[e]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // flush: one global atomic per nonzero tile value, periodic images resolved
+  const int ts0 = ts[0], ts01 = ts[0] * ts[1];
+  const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
+  for (int x = threadIdx.x; x < 6 * T; x += BLOCK) {
+    const Acc acc = tile[x];
+    if (acc == (Acc)0) continue;
+    const Real v = (Real)ldexp((double)acc, -esc);
+    const int comp = x / T;
+    int rem = x - comp * T;
+    const int iz = rem / ts01;
+    rem -= iz * ts01;
+    const int iy = rem / ts0;
+    const int ix = rem - iy * ts0;
+    int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gi[d] = ((gi[d] % g.n[d]) + g.n[d]) % g.n[d];
+    const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
+                     ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
+    atomic_add_r(A.dEB + gidx, v);
+  }
 }
 
 template <class Real>

@@ -9,6 +9,7 @@
 // global atomic.  When the box outgrows the tile (particles drifted far since
 // the last sort, or wrapped across a periodic boundary) the block deposits
 // with global atomics instead; both paths give the same sums.
+#include "block_util.h"
 #include "step_device.h"
 
 namespace picstep {
@@ -71,18 +72,6 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 }
 
 // ---------------------------------------------------------------- block -> chunk
-// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD
-// b mod 8), and each XCD has its own L2.  Block b = 8k + x is given the k-th
-// chunk of XCD x's contiguous share of the chunk sequence, so that one XCD
-// works through neighbouring chunks (neighbouring cells after the sort) and
-// its L2 holds the fields and current around them.
-constexpr int NXCD = 8;
-__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblk) {
-  const int64_t q = nblk / NXCD, r = nblk % NXCD;
-  const int64_t x = b % NXCD, k = b / NXCD;
-  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0) {
   const int64_t b = xcd_chunk(blockIdx.x, sp.blk0[MAXSP]);  // blk0[MAXSP] = all blocks
   s = 0;
@@ -91,80 +80,6 @@ __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int
     if (t < sp.nspec && b >= sp.blk0[t]) s = t;
   c0 = (b - sp.blk0[s]) * CHUNK;
   return c0 < sp.n[s];
-}
-
-// block-wide min/max of three ints (256 threads)
-__device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
-    }
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      red[w * 6 + d] = lo[d];
-      red[w * 6 + 3 + d] = hi[d];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = red[d];
-    hi[d] = red[3 + d];
-#pragma unroll
-    for (int ww = 1; ww < BLOCK / 64; ++ww) {
-      lo[d] = min(lo[d], red[ww * 6 + d]);
-      hi[d] = max(hi[d], red[ww * 6 + 3 + d]);
-    }
-  }
-}
-
-// block-wide maximum of a non-negative float (its bit pattern orders like
-// the value)
-__device__ __forceinline__ float block_max_nonneg(float v, int *red) {
-  int x = __float_as_int(v);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
-  __syncthreads();
-  x = red[0];
-#pragma unroll
-  for (int ww = 1; ww < BLOCK / 64; ++ww) x = max(x, red[ww]);
-  return __int_as_float(x);
-}
-
-// q = x / d for 0 <= x < 2^23 with a float reciprocal and one correction
-__device__ __forceinline__ int div_small(int x, int d, float inv) {
-  int q = (int)((float)x * inv);
-  if (q * d > x) --q;
-  else if ((q + 1) * d <= x) ++q;
-  return q;
-}
-
-// block-wide sum of three ints (256 threads)
-__device__ __forceinline__ void block_sum3(int v[3], int *red) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v[d] += __shfl_xor(v[d], o, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) red[w * 6 + d] = v[d];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    v[d] = 0;
-#pragma unroll
-    for (int ww = 0; ww < BLOCK / 64; ++ww) v[d] += red[ww * 6 + d];
-  }
 }
 
 // ---------------------------------------------------------------- per-particle steps
@@ -182,10 +97,6 @@ __device__ __forceinline__ bool in_tile(const DepTarget<Acc> &tile, const int ts
   return in;
 }
 
-// coefficient of a deposit into the tile: scaled by 2^esc for the
-// fixed-point accumulator of FP32 builds (exact power-of-two scaling)
-__device__ __forceinline__ float tile_coef(float C, int esc) { return ldexpf(C, esc); }
-__device__ __forceinline__ double tile_coef(double C, int) { return C; }
 
 template <class Real>
 using TileT = DepTarget<typename TileAcc<Real>::type>;

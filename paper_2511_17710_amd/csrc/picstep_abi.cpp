@@ -57,6 +57,7 @@ struct pic_ctx {
   double dx_min = 0;  // Sec. 2.4 CFL length
   int32_t ckpt_K = -1, ckpt_m = -1;  // last pic_forward_checkpointed
   int64_t ckpt_step0 = 0;
+  std::vector<int32_t> ckpt_sorts;  // steps n of that run that began with a sort
   bool timing = false;
   struct Ev {
     hipEvent_t a, b;
@@ -240,22 +241,29 @@ pic_status run_steps(pic_ctx *c, double dt, int32_t n, bool allow_sort) {
 
 bool isfin(double x) { return std::isfinite(x); }
 
-// ---- adjoint workspace: checkpoints, one segment of stored states, adjoints
+// ---- adjoint workspace: checkpoints, one segment of stored states, the
+// permutations of the sorts inside the run, adjoints and one spare array
 struct AdjLayout {
-  uint64_t slot, nck, seg, ckpt0, seg0, lam_u, lam_d, lamJ, total;
+  uint64_t slot, nck, seg, ckpt0, seg0, nperm, perm0, perm_bytes, lam_u, lam_d, tmp, lamJ, total;
 };
 
 AdjLayout adj_layout(const pic_ctx *c, int32_t K, int32_t m) {
   AdjLayout L{};
   const uint64_t ab = align_up(c->capacity * c->eb, ALIGN);
+  const int32_t S = c->d.sort_every;
   L.slot = align_up(c->ckpt_bytes, ALIGN);
   L.nck = (uint64_t)((K + m - 1) / m);
   L.seg = (uint64_t)std::min(K, m);
+  // K consecutive steps hold at most ceil(K / S) multiples of S
+  L.nperm = S > 0 ? (uint64_t)((K + S - 1) / S) : 0;
+  L.perm_bytes = align_up(c->capacity * 4, ALIGN);
   L.ckpt0 = 0;
   L.seg0 = L.nck * L.slot;
-  L.lam_u = L.seg0 + L.seg * L.slot;
+  L.perm0 = L.seg0 + L.seg * L.slot;
+  L.lam_u = L.perm0 + L.nperm * L.perm_bytes;
   L.lam_d = L.lam_u + 3 * ab;
-  L.lamJ = L.lam_d + 3 * ab;
+  L.tmp = L.lam_d + 3 * ab;
+  L.lamJ = L.tmp + ab;
   L.total = L.lamJ + align_up(3ull * c->g.npts * c->eb, ALIGN);
   return L;
 }
@@ -279,9 +287,10 @@ PSet<Real> slot_pset(const pic_ctx *c, char *slot) {
     p.u[a] = reinterpret_cast<Real *>(slot + o);
     o += ab;
   }
+  p.w = reinterpret_cast<Real *>(slot + o);
+  o += ab;
   p.phi = nullptr;
   if (c->g.geom != 0) p.phi = reinterpret_cast<Real *>(slot + o);
-  p.w = nullptr;
   return p;
 }
 
@@ -293,28 +302,53 @@ hipError_t copy_state(const pic_ctx *c, const PSet<Real> &dst, const PSet<Real> 
     e = hipMemcpyAsync(dst.offs[a], src.offs[a], n * sizeof(OffT<Real>), hipMemcpyDeviceToDevice, c->stream);
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
     e = hipMemcpyAsync(dst.u[a], src.u[a], n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst.w, src.w, n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->g.geom != 0)
     e = hipMemcpyAsync(dst.phi, src.phi, n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
   return e;
 }
 
+// The K steps exactly as pic_push_deposit runs them (sorts included); before
+// the sort of a step that starts a segment, the state is saved, so that a
+// segment's recompute replays the segment's sorts from the stored
+// permutations.
 template <class Real>
 pic_status fwd_ckpt(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws) {
   const AdjLayout L = adj_layout(c, K, m);
-  c->ckpt_K = K;
+  c->ckpt_K = -1;
   c->ckpt_m = m;
   c->ckpt_step0 = c->step;
+  c->ckpt_sorts.clear();
+  int32_t *perm = reinterpret_cast<int32_t *>(c->scratch + c->s_perm);
   for (int32_t n = 0; n < K; ++n) {
     if (n % m == 0) {
       hipError_t e = copy_state<Real>(c, slot_pset<Real>(c, ws + L.ckpt0 + (n / m) * L.slot),
                                       pset_of<Real>(c, c->active));
       if (e != hipSuccess) return hipchk(c, e, "checkpoint save");
     }
+    if (c->d.sort_every > 0 && c->step % c->d.sort_every == 0) {
+      if (c->ckpt_sorts.size() >= L.nperm) return fail(c, PIC_E_STATE, "sort count");
+      pic_status st = do_sort<Real>(c);
+      if (st != PIC_OK) return st;
+      hipError_t e = hipMemcpyAsync(ws + L.perm0 + c->ckpt_sorts.size() * L.perm_bytes, perm,
+                                    c->capacity * 4, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return hipchk(c, e, "store permutation");
+      c->ckpt_sorts.push_back(n);
+    }
     pic_status st = do_step<Real>(c, dt, n == K - 1, true);
     if (st != PIC_OK) return st;
     c->step += 1;
   }
+  c->ckpt_K = K;
   return PIC_OK;
+}
+
+// index of the stored permutation of the sort at step n of the run, or -1
+int sort_slot(const pic_ctx *c, int32_t n) {
+  for (size_t r = 0; r < c->ckpt_sorts.size(); ++r)
+    if (c->ckpt_sorts[r] == n) return (int)r;
+  return -1;
 }
 
 template <class Real>
@@ -330,6 +364,7 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
     ld[a] = reinterpret_cast<Real *>(ws + L.lam_d + a * ab);
   }
   Real *lJ = reinterpret_cast<Real *>(ws + L.lamJ);
+  Real *tmp = reinterpret_cast<Real *>(ws + L.tmp);
   Real *dE = static_cast<Real *>(dEB);
   hipError_t e = launch_zero<Real>(dE, 6 * g.npts, c->stream);
   for (int a = 0; a < 3 && e == hipSuccess; ++a) {
@@ -359,12 +394,25 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
   }
   A.lam_phi = nullptr;
   const int64_t saved_step = c->step;
+  const bool has_phi = c->o_phi != NONE;
   for (int64_t j = (int64_t)L.nck - 1; j >= 0; --j) {
     const int32_t s0 = (int32_t)(j * m), s1 = std::min(K, s0 + m);
-    e = copy_state<Real>(c, act, slot_pset<Real>(c, ws + L.ckpt0 + j * L.slot));
+    PSet<Real> cur = pset_of<Real>(c, c->active);
+    e = copy_state<Real>(c, cur, slot_pset<Real>(c, ws + L.ckpt0 + j * L.slot));
     if (e != hipSuccess) return hipchk(c, e, "checkpoint load");
     for (int32_t n = s0; n < s1; ++n) {
-      e = copy_state<Real>(c, slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot), act);
+      const int r = sort_slot(c, n);
+      if (r >= 0) {  // replay the step's sort from its stored permutation
+        const int32_t *pm = reinterpret_cast<const int32_t *>(ws + L.perm0 + r * L.perm_bytes);
+        const PSet<Real> dst = pset_of<Real>(c, c->active ^ 1);
+        for (int sp = 0; sp < c->nspec && e == hipSuccess; ++sp)
+          e = launch_gather<Real>(cur, dst, g.dim, has_phi, (int64_t)c->off[sp],
+                                  (int64_t)c->cnt[sp], pm + c->off[sp], c->stream);
+        if (e != hipSuccess) return hipchk(c, e, "sort replay");
+        c->active ^= 1;
+        cur = dst;
+      }
+      e = copy_state<Real>(c, slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot), cur);
       if (e != hipSuccess) return hipchk(c, e, "segment store");
       if (n < s1 - 1) {
         pic_status st = do_step<Real>(c, dt, false, false);
@@ -372,14 +420,25 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
       }
     }
     for (int32_t n = s1 - 1; n >= s0; --n) {
-      PSet<Real> st = slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot);
-      st.w = act.w;
-      A.p = st;
+      A.p = slot_pset<Real>(c, ws + L.seg0 + (n - s0) * L.slot);
       A.lamJ = (n == K - 1 && lamJ) ? lJ : nullptr;
       const int ev = ev_begin(c, 2);
       e = launch_adjoint_step<Real>(A, c->stream);
       ev_end(c, ev);
       if (e != hipSuccess) return hipchk(c, e, "adjoint step");
+      const int r = sort_slot(c, n);
+      if (r >= 0) {  // the adjoints follow their particles back to the order before the sort
+        const int32_t *pm = reinterpret_cast<const int32_t *>(ws + L.perm0 + r * L.perm_bytes);
+        Real *arr[6] = {lu[0], lu[1], lu[2], ld[0], ld[1], ld[2]};
+        for (int k = 0; k < 3 + g.dim && e == hipSuccess; ++k) {
+          for (int sp = 0; sp < c->nspec && e == hipSuccess; ++sp)
+            e = launch_scatter_back<Real>(arr[k], tmp, (int64_t)c->off[sp], (int64_t)c->cnt[sp],
+                                          pm + c->off[sp], c->stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(arr[k], tmp, cap * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+        }
+        if (e != hipSuccess) return hipchk(c, e, "adjoint permutation");
+      }
     }
   }
   e = launch_fold_ghosts<Real>(g, dE, 6, c->stream);
@@ -387,7 +446,8 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
     e = hipMemcpyAsync(static_cast<Real *>(du0) + a * cap, lu[a], cap * sizeof(Real),
                        hipMemcpyDeviceToDevice, c->stream);
   // leave the particles as they were at step 0 of the checkpointed run
-  if (e == hipSuccess) e = copy_state<Real>(c, act, slot_pset<Real>(c, ws + L.ckpt0));
+  if (e == hipSuccess)
+    e = copy_state<Real>(c, pset_of<Real>(c, c->active), slot_pset<Real>(c, ws + L.ckpt0));
   if (e != hipSuccess) return hipchk(c, e, "backward finish");
   (void)saved_step;
   c->step = c->ckpt_step0;
@@ -550,8 +610,8 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   c->s_stats = o;
   o += ALIGN;
   c->scratch_bytes = o;
-  // checkpoint: cell, offsets, u, phi
-  c->ckpt_bytes = ai + (uint64_t)d.dim * ab + 3 * ab + (d.geom != PIC_CART ? ab : 0);
+  // checkpoint: cell, offsets, u, w, phi
+  c->ckpt_bytes = ai + (uint64_t)d.dim * ab + 4 * ab + (d.geom != PIC_CART ? ab : 0);
   c->dx_min = cfl_length(g);
   *out = c;
   return PIC_OK;
@@ -972,6 +1032,32 @@ pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, c
     return fail(c, PIC_E_STATE, "backward(K=%d, m=%d) without a matching forward_checkpointed", K, m);
   return c->eb == 8 ? bwd<double>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0)
                     : bwd<float>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0);
+}
+
+pic_status pic_checkpointed_order(const pic_ctx *c, const void *ws, int32_t *dst) {
+  if (!c || !ws || !dst) return PIC_E_ARG;
+  if (c->ckpt_K < 1) return fail(c, PIC_E_STATE, "checkpointed_order before forward_checkpointed");
+  const AdjLayout L = adj_layout(c, c->ckpt_K, c->ckpt_m);
+  const uint64_t n = c->capacity;
+  std::vector<int32_t> order(n), perm(n), next(n);
+  for (uint64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  for (size_t r = 0; r < c->ckpt_sorts.size(); ++r) {
+    hipError_t e = hipMemcpyAsync(perm.data(), static_cast<const char *>(ws) + L.perm0 + r * L.perm_bytes,
+                                  n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hipchk(c, e, "checkpointed_order");
+    next = order;
+    for (int s = 0; s < c->nspec; ++s)
+      for (uint64_t i = 0; i < c->cnt[s]; ++i) {
+        const int32_t pl = perm[c->off[s] + i];
+        if (pl < 0 || (uint64_t)pl >= c->cnt[s])
+          return fail(c, PIC_E_STATE, "corrupt stored permutation");
+        next[c->off[s] + i] = order[c->off[s] + pl];
+      }
+    order.swap(next);
+  }
+  std::memcpy(dst, order.data(), n * 4);
+  return PIC_OK;
 }
 
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -250,6 +250,11 @@ __device__ __forceinline__ long long fixed_round(float v) {
   const double d = (double)v + 0x1.8p52;
   return __double_as_longlong(d) - 0x4338000000000000LL;
 }
+// coefficient of a contribution to a tile: scaled by 2^esc for the
+// fixed-point accumulator of FP32 builds (exact power-of-two scaling)
+__device__ __forceinline__ float tile_coef(float C, int esc) { return ldexpf(C, esc); }
+__device__ __forceinline__ double tile_coef(double C, int) { return C; }
+
 __device__ __forceinline__ void atomic_add_r(long long *p, float v) {
   atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)fixed_round(v));
 }

@@ -97,6 +97,7 @@ def lib():
             "pic_adjoint_workspace": [vp, i32, i32, C.POINTER(u64)],
             "pic_forward_checkpointed": [vp, dbl, i32, i32, vp],
             "pic_backward": [vp, dbl, i32, i32, vp, vp, vp, vp, vp],
+            "pic_checkpointed_order": [vp, vp, vp],
             "pic_last_error": [vp],
             "pic_timing_enable": [vp, i32],
             "pic_timing_read": [vp, C.POINTER(Timing)],
@@ -259,7 +260,8 @@ class Context:
         return nb.value
 
     def forward_checkpointed(self, dt, K, m):
-        """K steps without sorting; the state is kept every m steps in a
+        """K steps as push_deposit runs them (sorts included); the state is
+        kept every m steps, with every sort's permutation, in a
         torch-allocated workspace for backward()."""
         nb = self.adjoint_workspace(K, m)
         ws = getattr(self, "_ws", None)
@@ -293,6 +295,15 @@ class Context:
                     "backward")
         torch.cuda.current_stream(self.device).synchronize()
         return dEB, du0
+
+    def checkpointed_order(self):
+        """int32 [capacity]: for each particle slot at step K of the last
+        forward_checkpointed, its slot at step 0."""
+        out = np.zeros(self.layout().capacity, dtype=np.int32)
+        self._check(lib().pic_checkpointed_order(self.h, C.c_void_p(self._ws.data_ptr()),
+                                                 out.ctypes.data_as(C.c_void_p)),
+                    "checkpointed_order")
+        return out
 
     def timing_enable(self, on=True):
         self._check(lib().pic_timing_enable(self.h, 1 if on else 0), "timing_enable")

@@ -75,6 +75,65 @@ def test_adjoint_matches_reference(dim, K, m, prec):
     assert eu < tol, eu
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adjoint_with_sorts_inside_the_map(dim, prec):
+    """Sorts every 2 steps inside K = 7 steps checkpointed every 3: the
+    segments replay the stored permutations and the particle adjoints follow
+    every sort back.  lam_u is given in the order at step K (mapped through
+    checkpointed_order from per-particle values); du0 comes back in the order
+    at step 0 and is compared with the reference adjoint of the unsorted map
+    (each particle's gradient does not depend on the order)."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[adjoint] sorts inside dim={dim} {prec}", flush=True)
+    K, m, S = 7, 3, 2
+    wl = _case(dim, K, 50 + dim)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    lamJ, lam_u = _weights(wl, 11)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    ref = O.adjoint(g, dt, K, EB, wl.species, lamJ, lam_u=lam_u)
+    _, Jref = O.run(g, dt, K, EB, wl.species, sort_every=S)
+    ctx = P.from_workload(wl, prec=prec, sort_every=S)
+    ctx.forward_checkpointed(dt, K, m)
+    J = ctx.current_host().astype(np.float64)
+    L = ctx.layout()
+    order = ctx.checkpointed_order()
+    lu0 = np.zeros((3, L.capacity))
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        lu0[:, o:o + lam.shape[0]] = lam.T
+    moved = 0
+    for s, lam in enumerate(lam_u):
+        o, n = L.species_offset[s], lam.shape[0]
+        seg = order[o:o + n]
+        assert np.array_equal(np.sort(seg), np.arange(o, o + n))  # a permutation of the species
+        moved += int(np.sum(seg != np.arange(o, o + n)))
+    assert moved > 0  # the sorts did reorder particles
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    lu = torch.from_numpy(lu0[:, order].copy()).to(dtype=dtype, device="cuda")
+    dEB, du0 = ctx.backward(dt, K, m, torch.from_numpy(lamJ).to(dtype=dtype, device="cuda"), lu)
+    dEB = dEB.double().cpu().numpy()
+    du0 = du0.double().cpu().numpy()
+    du = [du0[:, L.species_offset[s]:L.species_offset[s] + lam.shape[0]].T
+          for s, lam in enumerate(lam_u)]
+    eJ = U.rel_l2(J, Jref)
+    eE = U.rel_l2(dEB, ref["dEB"])
+    eu = U.rel_l2(np.concatenate(du), np.concatenate(ref["du0"]))
+    print(f"  J {eJ:.2e} dEB {eE:.2e} du0 {eu:.2e}", flush=True)
+    tol = 1e-10 if prec == "f64" else 1e-3
+    assert eJ < (1e-10 if prec == "f64" else 1e-5)
+    assert eE < tol, eE
+    assert eu < tol, eu
+    # the particles are back at their step-0 state and order
+    for s in range(len(wl.species)):
+        q = ctx.particles_get(s)
+        np.testing.assert_array_equal(q["cell"][:, :dim], wl.species[s]["cell"][:, :dim])
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     """Recomputing from checkpoints reproduces the stored trajectory exactly:
     du0 is bitwise equal for m = K and m = 1; dEB agrees up to the order of
