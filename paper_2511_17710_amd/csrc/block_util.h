@@ -19,6 +19,15 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblk) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// v mod n in [0, n): tile coordinates lie within one period of the active
+// range except on tiny grids, which take the general remainder
+__device__ __forceinline__ int wrap_periodic(int v, int n) {
+  v += (v < 0) ? n : 0;
+  v -= (v >= n) ? n : 0;
+  if ((unsigned)v >= (unsigned)n) v = ((v % n) + n) % n;
+  return v;
+}
+
 // block-wide min/max of three ints (256 threads)
 __device__ __forceinline__ void block_minmax3(int lo[3], int hi[3], int *red) {
 #pragma unroll

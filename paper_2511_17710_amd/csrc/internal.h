@@ -19,12 +19,14 @@ struct GridConst {
   int np[3];
   int64_t npts;
   double dx[3];                 // Cartesian cell sizes (1 for unused dims)
+  double inv_dx[3];             // 1 / dx
   double rmin, dr, dth;         // spherical: r = rmin + x1 dr, theta = x2 dth
   double Rmin, dR, dT, r0, vt;  // quasi-spherical: r = r0 + exp(Rmin + x1 dR), T = x2 dT
   int fp64_cells;               // FP32 curvilinear: cells near theta=0,pi and r_min done in FP64
   int shift2, shift3;           // cell packing
   int32_t mask1, mask2, mask3;
   int brick[3];                 // sort order: cells brick by brick (4^3 in 3D, 8^2 in 2D)
+  int brick_shift[3];           // log2(brick)
   int nbrick[3];
 };
 

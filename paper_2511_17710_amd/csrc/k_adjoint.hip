@@ -162,7 +162,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const Real dx = dtr * un[a] * ig / (Real)g.dx[a];  // as in the forward kernel
+    const Real dx = cart_disp(g, a, dtr, un[a], ig);  // as in the forward kernel
     OffT<Real> qn;
     m[a] = PS::move(q[a], (double)dx, qn);
     za[a] = PS::exact(q[a]);
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     const int ix = rem - iy * ts0;
     int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) gi[d] = ((gi[d] % g.n[d]) + g.n[d]) % g.n[d];
+    for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
     const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
                      ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
     atomic_add_r(A.dEB + gidx, v);

@@ -139,10 +139,12 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, int s, int
   int inew[3] = {i[0], i[1], i[2]};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const Real dx = dtr * u[a] * gi / (Real)g.dx[a];
+    const Real dx = cart_disp(g, a, dtr, u[a], gi);
     OffT<Real> qn;
     m[a] = PS::move(q[a], (double)dx, qn);
-    span = fmaxf(span, (float)fabs(PS::exact(qn) + (double)m[a] - PS::exact(q[a])));
+    // bound of the stored displacement: |dx| plus the rounding of the new
+    // offset (2^-32 in the FP32 build, an ulp of 1 in the FP64 one)
+    span = fmaxf(span, fabsf((float)dx) * 1.0001f + 0x1p-31f);
     q[a] = qn;
     int v = i[a] + m[a];
     v = (v < 0) ? v + g.n[a] : ((v >= g.n[a]) ? v - g.n[a] : v);  // periodic wrap
@@ -249,7 +251,7 @@ __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, int s, int3
   m[1] = inew[1] - i[1];
   const bool alive = inew[0] >= 0 && inew[0] < g.n[0];  // radial exit
   span = fmaxf(span, (float)fabs(PS::exact(qn1) + (double)m[0] - PS::exact(q[0])));
-  span = fmaxf(span, (float)fabs(PS::exact(qn2) + (double)m[1] - PS::exact(q[1])));
+  span = fmaxf(span, (float)fabs(PS::exact(qn2) + (double)m[1] - PS::exact(q[1])));  // theta clamp
   q[0] = qn1;
   q[1] = qn2;
   phi = phinew;
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
       int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
       if (GEOM == 0) {  // periodic: add straight into the image in the active region
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) gi[d] = ((gi[d] % g.n[d]) + g.n[d]) % g.n[d];
+        for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
       }
       const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
                        ((DIM == 3) ? np01 * (gi[2] + NG) : 0);

@@ -1,11 +1,12 @@
 // k_sort.hip -- stable per-cell counting sort of a particle species.
 //
 // Least-significant-digit radix sort on a cell key that orders cells brick by
-// brick (8-bit digits, dead particles carry the largest key), so equal keys
-// keep their previous order and the permutation is unique.  Per pass: tile histograms (digit-major
-// matrix), one exclusive scan of that matrix, and a stable in-tile ranking
-// with wave ballots followed by a scatter.  A gather then reorders
-// every SoA array into the second particle set.
+// brick (8-bit digits; dead particles carry the largest key; the first pass
+// forms the keys from the cells), so equal keys keep their previous order and
+// the permutation is unique.  Per pass: tile histograms (digit-major matrix),
+// one exclusive scan of that matrix, and a stable in-tile ranking with wave
+// ballots followed by a scatter.  A gather then reorders every SoA array into
+// the second particle set.
 #include "internal.h"
 
 namespace picstep {
@@ -38,33 +39,38 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh_w
   return pre + x - v;
 }
 
-// keys of one species range: cells brick by brick (brick index, then the cell
-// inside the brick, x fastest in both), or 1 << (keybits - 1) when dead
-__global__ __launch_bounds__(SORT_THREADS) void k_make_keys(GridConst g,
-                                                            const int32_t *__restrict__ cell,
-                                                            int64_t n, uint32_t deadkey,
-                                                            uint32_t *__restrict__ keys,
-                                                            int32_t *__restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
-  if (i >= n) return;
-  const int32_t c = cell[i];
-  uint32_t key = deadkey;
-  if (!(c & DEAD_BIT)) {
-    const int ii[3] = {(c & g.mask1) - 1, (c >> g.shift2) & g.mask2, (c >> g.shift3) & g.mask3};
-    const uint32_t bi[3] = {(uint32_t)(ii[0] / g.brick[0]), (uint32_t)(ii[1] / g.brick[1]),
-                            (uint32_t)(ii[2] / g.brick[2])};
-    const uint32_t li[3] = {(uint32_t)(ii[0] % g.brick[0]), (uint32_t)(ii[1] % g.brick[1]),
-                            (uint32_t)(ii[2] % g.brick[2])};
-    const uint32_t brick = bi[0] + (uint32_t)g.nbrick[0] * (bi[1] + (uint32_t)g.nbrick[1] * bi[2]);
-    const uint32_t local = li[0] + (uint32_t)g.brick[0] * (li[1] + (uint32_t)g.brick[1] * li[2]);
-    key = brick * (uint32_t)(g.brick[0] * g.brick[1] * g.brick[2]) + local;
-  }
-  keys[i] = key;
-  vals[i] = (int32_t)i;
+// key of a cell: cells brick by brick (brick index, then the cell inside the
+// brick, x fastest in both), or deadkey = 1 << (keybits - 1) when dead; brick
+// sides are powers of two
+__device__ __forceinline__ uint32_t brick_key(const GridConst &g, int32_t c, uint32_t deadkey) {
+  if (c & DEAD_BIT) return deadkey;
+  const uint32_t ii[3] = {(uint32_t)((c & g.mask1) - 1), (uint32_t)((c >> g.shift2) & g.mask2),
+                          (uint32_t)((c >> g.shift3) & g.mask3)};
+  const int s0 = g.brick_shift[0], s1 = g.brick_shift[1], s2 = g.brick_shift[2];
+  const uint32_t brick = (ii[0] >> s0) + (uint32_t)g.nbrick[0] * ((ii[1] >> s1) +
+                         (uint32_t)g.nbrick[1] * (ii[2] >> s2));
+  const uint32_t local = (ii[0] & ((1u << s0) - 1)) | ((ii[1] & ((1u << s1) - 1)) << s0) |
+                         ((ii[2] & ((1u << s2) - 1)) << (s0 + s1));
+  return (brick << (s0 + s1 + s2)) | local;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__restrict__ keys,
-                                                             int64_t n, int shift,
+// The first radix pass reads the cells and forms key and index on the fly
+// (cells != nullptr); later passes read the previous pass's keys and values.
+struct KeySource {
+  const uint32_t *keys;
+  const int32_t *vals;
+  const int32_t *cells;
+  GridConst g;
+  uint32_t deadkey;
+  __device__ __forceinline__ uint32_t key(int64_t i) const {
+    return cells ? brick_key(g, cells[i], deadkey) : keys[i];
+  }
+  __device__ __forceinline__ int32_t val(int64_t i) const {
+    return cells ? (int32_t)i : vals[i];
+  }
+};
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(KeySource src, int64_t n, int shift,
                                                              int32_t *__restrict__ hist,
                                                              int64_t ntiles) {
   __shared__ int h[RADIX];
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t *__r
 #pragma unroll
   for (int j = 0; j < SORT_ITEMS; ++j) {
     const int64_t i = t0 + (int64_t)j * SORT_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1);
+    if (i < n) atomicAdd(&h[(src.key(i) >> shift) & (RADIX - 1)], 1);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
@@ -144,9 +150,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_scan_add(int32_t *__restrict__
 // tile is then staged in digit order in LDS and written out with consecutive
 // threads on consecutive destinations.
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
-    const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, uint32_t *__restrict__ kout,
-    int32_t *__restrict__ vout, int64_t n, int shift, const int32_t *__restrict__ hist,
-    int64_t ntiles) {
+    KeySource src, uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n, int shift,
+    const int32_t *__restrict__ hist, int64_t ntiles) {
   constexpr int NW = SORT_THREADS / 64;
   constexpr int PER_WAVE = SORT_TILE / NW;
   constexpr int ROUNDS = PER_WAVE / 64;
@@ -171,8 +176,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
   for (int j = 0; j < ROUNDS; ++j) {
     const int e = w * PER_WAVE + j * 64 + lane;
     const bool ok = e < nvalid;
-    k[j] = ok ? kin[t0 + e] : 0u;
-    v[j] = ok ? vin[t0 + e] : -1;
+    k[j] = ok ? src.key(t0 + e) : 0u;
+    v[j] = ok ? src.val(t0 + e) : -1;
     const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
     uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -245,52 +250,70 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
   const int64_t nchunks = (L + SCAN_CHUNK - 1) / SCAN_CHUNK;
   if (nchunks > SCAN_CHUNK) return hipErrorInvalidValue;
   const uint32_t deadkey = 1u << (keybits - 1);
-  hipLaunchKernelGGL(k_make_keys, dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)),
-                     dim3(SORT_THREADS), 0, s, g, cell, n, deadkey, S.keys[0], S.vals[0]);
   const int passes = (keybits + 7) / 8;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = 8 * ps;
     const int src = ps & 1, dst = src ^ 1;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
-                       S.keys[src], n, shift, S.hist, ntiles);
+    KeySource ks{S.keys[src], S.vals[src], ps == 0 ? cell : nullptr, g, deadkey};
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks, n,
+                       shift, S.hist, ntiles);
     hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist,
                        L, S.bsum);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SORT_THREADS), 0, s, S.bsum, (int)nchunks);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist, L,
                        S.bsum);
     int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
-                       S.keys[src], S.vals[src], S.keys[dst], vdst, n, shift, S.hist, ntiles);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks,
+                       S.keys[dst], vdst, n, shift, S.hist, ntiles);
   }
   return hipGetLastError();
 }
 
-// reorder every SoA array of one species range: dst[off+i] = src[off+perm[i]]
+// reorder every SoA array of one species range: dst[off+i] = src[off+perm[i]].
+// Four elements per thread, strided by the block size (coalesced stores),
+// with all loads of an array issued before its stores.
+constexpr int GATHER_PER_THREAD = 4;
+
+template <class T>
+__device__ __forceinline__ void gather_array(const T *__restrict__ src, T *__restrict__ dst,
+                                             int64_t off, const int64_t i[GATHER_PER_THREAD],
+                                             const int32_t pj[GATHER_PER_THREAD]) {
+  T v[GATHER_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < GATHER_PER_THREAD; ++k)
+    if (pj[k] >= 0) v[k] = src[off + pj[k]];
+#pragma unroll
+  for (int k = 0; k < GATHER_PER_THREAD; ++k)
+    if (pj[k] >= 0) dst[off + i[k]] = v[k];
+}
+
 template <class Real>
 __global__ __launch_bounds__(SORT_THREADS) void k_gather(PSet<Real> src, PSet<Real> dst, int dim,
                                                          int has_phi, int64_t off, int64_t n,
                                                          const int32_t *__restrict__ perm) {
-  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
-  if (i >= n) return;
-  const int32_t pi = perm[i];
-  if (pi < 0 || pi >= n) return;  // never read outside the species range
-  const int64_t j = off + pi;
-  const int64_t o = off + i;
-  dst.cell[o] = src.cell[j];
-  for (int a = 0; a < dim; ++a) dst.offs[a][o] = src.offs[a][j];
-  dst.u[0][o] = src.u[0][j];
-  dst.u[1][o] = src.u[1][j];
-  dst.u[2][o] = src.u[2][j];
-  dst.w[o] = src.w[j];
-  if (has_phi) dst.phi[o] = src.phi[j];
+  int64_t i[GATHER_PER_THREAD];
+  int32_t pj[GATHER_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < GATHER_PER_THREAD; ++k) {
+    i[k] = ((int64_t)blockIdx.x * GATHER_PER_THREAD + k) * SORT_THREADS + threadIdx.x;
+    pj[k] = (i[k] < n) ? perm[i[k]] : -1;
+    if (pj[k] >= n) pj[k] = -1;  // never read outside the species range
+  }
+  gather_array(src.cell, dst.cell, off, i, pj);
+  for (int a = 0; a < dim; ++a) gather_array(src.offs[a], dst.offs[a], off, i, pj);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) gather_array(src.u[a], dst.u[a], off, i, pj);
+  gather_array(src.w, dst.w, off, i, pj);
+  if (has_phi) gather_array(src.phi, dst.phi, off, i, pj);
 }
 
 template <class Real>
 hipError_t launch_gather(const PSet<Real> &src, const PSet<Real> &dst, int dim, int has_phi,
                          int64_t off, int64_t n, const int32_t *perm, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gather<Real>), dim3((unsigned)((n + SORT_THREADS - 1) / SORT_THREADS)),
-                     dim3(SORT_THREADS), 0, s, src, dst, dim, has_phi, off, n, perm);
+  const int64_t per = (int64_t)SORT_THREADS * GATHER_PER_THREAD;
+  hipLaunchKernelGGL((k_gather<Real>), dim3((unsigned)((n + per - 1) / per)), dim3(SORT_THREADS),
+                     0, s, src, dst, dim, has_phi, off, n, perm);
   return hipGetLastError();
 }
 

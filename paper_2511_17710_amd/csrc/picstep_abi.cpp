@@ -520,6 +520,7 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
     g.n[a] = a < d.dim ? d.n[a] : 1;
     g.np[a] = a < d.dim ? d.n[a] + 2 * NG : 1;
     g.dx[a] = (d.geom == PIC_CART && a < d.dim) ? (d.hi[a] - d.lo[a]) / d.n[a] : 1.0;
+    g.inv_dx[a] = 1.0 / g.dx[a];
   }
   g.npts = (int64_t)g.np[0] * g.np[1] * g.np[2];
   if (6 * g.npts >= (int64_t(1) << 31)) {  // device index math is 32-bit
@@ -553,6 +554,7 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   // sort order: 4x4x4 bricks in 3D, 8x8 in 2D
   for (int a = 0; a < 3; ++a) {
     g.brick[a] = a < d.dim ? (d.dim == 3 ? 4 : 8) : 1;
+    g.brick_shift[a] = a < d.dim ? (d.dim == 3 ? 2 : 3) : 0;
     g.nbrick[a] = (g.n[a] + g.brick[a] - 1) / g.brick[a];
   }
   const int64_t nkeys = (int64_t)g.nbrick[0] * g.nbrick[1] * g.nbrick[2] *

@@ -141,6 +141,18 @@ __device__ __forceinline__ void boris(Real k, const Real E[3], const Real B[3], 
   u[2] = um2 + (up0 * s1 - up1 * s0) + k * E[2];
 }
 
+// Cartesian in-cell displacement dt u_a / (gamma Delta_a) (steps 6-7); the
+// FP32 build multiplies by the reciprocal spacing, the FP64 build divides
+// (it matches the reference's rounding).  The forward and the adjoint
+// recompute share this routine, so both take the same step.
+__device__ __forceinline__ float cart_disp(const GridConst &g, int a, float dt, float u, float gi) {
+  return dt * u * gi * (float)g.inv_dx[a];
+}
+__device__ __forceinline__ double cart_disp(const GridConst &g, int a, double dt, double u,
+                                            double gi) {
+  return dt * u * gi / g.dx[a];
+}
+
 // ---------------------------------------------------------------- positions
 // Offset codec and canonicalisation (cell index + offset in [0,1), Sec. 3.1).
 // FP32 build: the offset is q * 2^-32; the weights use it rounded to float,
