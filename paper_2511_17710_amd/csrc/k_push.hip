@@ -281,7 +281,11 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
     zb[a] = PS::exact(qn[a]) + (double)m[a];
   }
   ZigZag<Real> z;
-  zigzag<DIM, Real>(za, m, zb, z);
+  const int nseg = (m[0] | m[1] | m[2]) ? 2 : 1;
+  if (nseg == 1)
+    straight<DIM, Real>(za, zb, z);
+  else
+    zigzag<DIM, Real>(za, m, zb, z);
   int ib[3] = {i[0], i[1], i[2]};
   if (GEOM == 0) {
 #pragma unroll
@@ -290,9 +294,9 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
   }
   const Real C = (Real)A.sp.qdt[s] * w;
   if (in_tile<DIM>(tile, ts, ib)) {
-    deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3);
+    deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3, nseg);
   } else {
-    deposit<DIM>(glob, C, i, m, z, dx3);
+    deposit<DIM>(glob, C, i, m, z, dx3, nseg);
     if (A.stats) atomicAdd(A.stats + 1, 1);
   }
 }

@@ -224,6 +224,16 @@ struct ZigZag {
   Real W[2][3];
 };
 
+// the whole in-cell step a -> b as segment 0 (used when m = 0 in every dimension)
+template <int DIM, class Real>
+__device__ __forceinline__ void straight(const double a[3], const double b[3], ZigZag<Real> &z) {
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    z.F[0][d] = (Real)(b[d] - a[d]);
+    z.W[0][d] = (Real)((a[d] + b[d]) * 0.5);
+  }
+}
+
 // a, b: exact old offset and new offset + m (both measured from the old cell)
 template <int DIM, class Real>
 __device__ __forceinline__ void zigzag(const double a[3], const int m[3], const double b[3],
@@ -283,12 +293,16 @@ struct DepTarget {
 
 // Scatter of the two zig-zag segments (indices may reach the ghost layer of
 // the global array; periodic ghosts are folded after the step).
+// nseg = 1: a step that stays in its cell is one straight segment (the two
+// collinear halves of the zig-zag carry, summed, exactly its flux).
 template <int DIM, class Real, class Acc>
 __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const int i0[3],
-                                        const int m[3], const ZigZag<Real> &z, Real dx3) {
+                                        const int m[3], const ZigZag<Real> &z, Real dx3,
+                                        int nseg = 2) {
   const int cs = t.cs, sy = t.sy, sz = t.sz;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
+    if (s >= nseg) break;
     const int I = i0[0] + (s ? m[0] : 0) - t.o[0];
     const int Jc = i0[1] + (s ? m[1] : 0) - t.o[1];
     const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) - t.o[2] : 0;
@@ -301,7 +315,7 @@ __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const i
       atomic_add_r(t.J + base + sy, cx * Wy);
       atomic_add_r(t.J + cs + base, cy * ((Real)1 - Wx));
       atomic_add_r(t.J + cs + base + 1, cy * Wx);
-      const Real h = C * dx3 * (Real)0.5;
+      const Real h = C * dx3 * (nseg == 1 ? (Real)1 : (Real)0.5);  // dx3 shared by the segments
       const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
       Acc *J3 = t.J + 2 * cs + base;
       atomic_add_r(J3, h * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy));
