@@ -19,6 +19,19 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblk) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// largest s with s^dim <= vals
+constexpr int tile_side(int vals, int dim) {
+  int s = 1;
+  while (true) {
+    int p = 1;
+    for (int d = 0; d < dim; ++d) p *= s + 1;
+    if (p > vals) return s;
+    ++s;
+  }
+}
+static_assert(tile_side(1331, 3) == 11 && tile_side(1330, 3) == 10 && tile_side(1365, 2) == 36,
+              "tile_side");
+
 // v mod n in [0, n): tile coordinates lie within one period of the active
 // range except on tiny grids, which take the general remainder
 __device__ __forceinline__ int wrap_periodic(int v, int n) {

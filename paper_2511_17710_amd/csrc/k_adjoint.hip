@@ -97,8 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     block_sum3(sum, red);
     __syncthreads();
     block_sum3(nl, red);
-    static_assert(sizeof(Acc) == 8, "fallback tile sides assume 8-byte accumulators");
-    constexpr int SIDE = (DIM == 3) ? 8 : 26;  // 6 SIDE^DIM <= TILE_VALS
+    constexpr int SIDE = tile_side(TILE_VALS / 6, DIM);  // 6 SIDE^DIM <= TILE_VALS
     T = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {

@@ -399,8 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     block_sum3(sum, red);
     __syncthreads();
     block_sum3(nl, red);
-    static_assert(sizeof(Acc) == 8, "fallback tile sides assume 8-byte accumulators");
-    constexpr int SIDE = (DIM == 3) ? 11 : 36;  // 3 SIDE^DIM <= TILE_VALS
+    constexpr int SIDE = tile_side(TILE_VALS / 3, DIM);  // 3 SIDE^DIM <= TILE_VALS
     T = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
