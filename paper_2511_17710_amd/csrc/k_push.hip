@@ -9,6 +9,8 @@
 // global atomic.  When the box outgrows the tile (particles drifted far since
 // the last sort, or wrapped across a periodic boundary) the block deposits
 // with global atomics instead; both paths give the same sums.
+#include <type_traits>
+
 #include "block_util.h"
 #include "step_device.h"
 
@@ -111,8 +113,26 @@ __device__ __forceinline__ void unpack_m(int p, int m[3]) {
   m[2] = ((p >> 4) & 3) - 1;
 }
 
-template <int DIM, class Real>
-__device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, int s, int32_t c,
+// fields at the particle: from the block's LDS copy (FT: it covers every
+// live particle's stencil), else from global memory
+template <int DIM, class Real, bool FT>
+__device__ __forceinline__ void particle_fields(const StepArgs<Real> &A, const FieldTile<Real> &ft,
+                                                const int i[3], const int shift[3],
+                                                const Stencil1<Real> st[3], Real F[6]) {
+  if (FT) {
+    int dsh[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      if (shift[a] && i[a] < (A.g.n[a] >> 1)) dsh[a] = A.g.n[a];
+    interp6_tile<DIM, Real>(ft, dsh, st, F);
+  } else {
+    interp6<DIM, Real>(A.EB, A.g, st, F);
+  }
+}
+
+template <int DIM, class Real, bool FT>
+__device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
+                                             const int shift[3], int s, int32_t c,
                                              OffT<Real> q[3], Real u[3], int &mp, Real &dx3,
                                              float &span) {
   using PS = Pos<Real>;
@@ -123,7 +143,7 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, int s, int
 #pragma unroll
   for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], (Real)PS::weight(q[a]));
   Real F[6];
-  interp6<DIM, Real>(A.EB, g, st, F);
+  particle_fields<DIM, Real, FT>(A, ft, i, shift, st, F);
   Real E[3], B[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -202,10 +222,10 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
   return pr;
 }
 
-template <int GEOM, class Real>
-__device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, int s, int32_t c,
-                                            OffT<Real> q[3], Real u[3], Real &phi, int &mp,
-                                            Real &dx3, float &span) {
+template <int GEOM, class Real, bool FT>
+__device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
+                                            int s, int32_t c, OffT<Real> q[3], Real u[3],
+                                            Real &phi, int &mp, Real &dx3, float &span) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   int i[3];
@@ -215,7 +235,8 @@ __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, int s, int3
   st[0] = stencil1(i[0], d1);
   st[1] = stencil1(i[1], d2);
   Real F[6];
-  interp6<2, Real>(A.EB, g, st, F);
+  const int noshift[3] = {0, 0, 0};
+  particle_fields<2, Real, FT>(A, ft, i, noshift, st, F);
   const Real k = (Real)A.sp.k[s];
   double dx1, dx2;
   Real phinew;
@@ -302,11 +323,29 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
 }
 
 // ---------------------------------------------------------------- the kernel
+// Waves per SIMD the register allocation must allow: the 32 KB LDS buffer
+// already limits a CU to 4 blocks of 4 waves, and the Cartesian FP32 kernel
+// runs faster capped at that occupancy (128 VGPRs, a few spills) than
+// uncapped at 3 waves; the other instances would spill heavily.
 template <int GEOM, int DIM, class Real>
-__global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
+constexpr int push_waves() {
+  return (GEOM == 0 && sizeof(Real) == 4) ? 4 : 1;
+}
+
+template <int GEOM, int DIM, class Real>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(push_waves<GEOM, DIM, Real>(), 8)))
+void k_push(StepArgs<Real> A) {
   using Acc = typename TileAcc<Real>::type;
   constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Acc);
-  __shared__ Acc tile[TILE_VALS];
+  constexpr int FIELD_VALS = TILE_BYTES / (int)sizeof(Real);
+  // one LDS buffer: the block's copy of the fields during the push pass,
+  // then its current tile during the deposit pass
+  __shared__ union {
+    Acc j[TILE_VALS];
+    Real f[FIELD_VALS];
+  } lds;
+  Acc *tile = lds.j;
+  Real *ftile = lds.f;
   __shared__ int red[6 * (BLOCK / 64)];
   const GridConst &g = A.g;
   int s;
@@ -372,20 +411,28 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
       block_minmax3(lo, hi, red);
     }
   }
-  // tile placement: the whole box when it fits, else the largest cube (square
-  // in 2D) centred on the chunk's mean cell; particles whose stencil leaves
-  // the tile deposit with global atomics
-  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1};
-  int64_t T = 1;
+  // tile placement, for the field copy (stencils reach cell - 1 ... cell + 1)
+  // and the current (cell - 1 ... cell + 2): the whole box when it fits, else
+  // the largest cube (square in 2D) centred on the chunk's mean cell;
+  // particles whose stencil leaves a tile read or deposit in global memory
+  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1}, f0[3] = {0, 0, 0}, fs[3] = {1, 1, 1};
+  int64_t T = 1, TF = 1;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    ts[d] = hi[d] - lo[d] + 4;  // stencils reach cell - 1 ... cell + 2
+    ts[d] = hi[d] - lo[d] + 4;
+    fs[d] = hi[d] - lo[d] + 3;
     T *= ts[d];
+    TF *= fs[d];
   }
-  if (3 * T <= TILE_VALS) {
+  const bool fit_j = 3 * T <= TILE_VALS;
+  // the field copy is made only when the whole box fits, in FP32 builds
+  const bool use_ft = sizeof(Real) == 4 && 6 * TF <= FIELD_VALS;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) t0[d] = lo[d] - 1;
-  } else {
+  for (int d = 0; d < DIM; ++d) {
+    t0[d] = lo[d] - 1;
+    f0[d] = lo[d] - 1;
+  }
+  if (!fit_j) {  // uniform
     __syncthreads();
     int sum[3] = {0, 0, 0}, nl[3] = {0, 0, 0};
 #pragma unroll
@@ -410,6 +457,43 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
     }
   }
 
+  // copy the fields of the box (plus the stencil halo) into LDS (periodic
+  // images on Cartesian grids; on curvilinear grids points outside the
+  // padded lattice, which no particle stencil reaches, are left zero)
+  FieldTile<Real> ft;
+  ft.F = ftile;
+  ft.T = (int)TF;
+  ft.sy = fs[0];
+  ft.sz = fs[0] * fs[1];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ft.o[d] = f0[d];
+    ft.ts[d] = fs[d];
+  }
+  if (use_ft) {
+    const int Tf = (int)TF, fs0 = fs[0], fs01 = fs[0] * fs[1];
+    const float iT = 1.0f / (float)Tf, i0f = 1.0f / (float)fs0, i01 = 1.0f / (float)fs01;
+    for (int x = threadIdx.x; x < 6 * Tf; x += BLOCK) {
+      const int comp = div_small(x, Tf, iT);
+      int rem = x - comp * Tf;
+      const int iz = div_small(rem, fs01, i01);
+      rem -= iz * fs01;
+      const int iy = div_small(rem, fs0, i0f);
+      const int ix = rem - iy * fs0;
+      int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        if (GEOM == 0)
+          gi[d] = wrap_periodic(gi[d], g.n[d]);
+        else
+          ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
+      }
+      ftile[x] = ok ? A.EB[comp * (int)g.npts + pad_index(g, gi[0], gi[1], gi[2], DIM)] : (Real)0;
+    }
+    __syncthreads();
+  }
+
   Real uu[3][PPT], ww[PPT], ph[PPT];
 #pragma unroll
   for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
@@ -418,44 +502,50 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
 
   const bool use_tile = A.deposit != 0;
   if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
-  if (use_tile)
-    for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Acc)0;
 
   // pass 1: interpolate, rotate, push and move every particle of the thread
-  // (steps 3-7), keeping the old position for the deposit
+  // (steps 3-7), keeping the old position for the deposit; two instances,
+  // with the fields from LDS or from global memory
   int32_t co[PPT];
   OffT<Real> qo[3][PPT];
   int mp[PPT];
   Real d3[PPT];
   float bmax = 0.0f;
   const Real qdt = (Real)A.sp.qdt[s];
+  auto push_pass = [&](auto from_lds) {
+    constexpr bool FT = decltype(from_lds)::value;
 #pragma unroll
-  for (int r = 0; r < PPT; ++r) {
-    co[r] = cl[r];
-    mp[r] = 0;
-    d3[r] = (Real)0;
+    for (int r = 0; r < PPT; ++r) {
+      co[r] = cl[r];
+      mp[r] = 0;
+      d3[r] = (Real)0;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) qo[a][r] = qd[a][r];
-    if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
-    OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
-                       DIM > 2 ? qd[2][r] : (OffT<Real>)0};
-    Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
-    float span = 0.0f;
-    Real dx3;
-    if (GEOM == 0) {
-      cl[r] = cart_push<DIM, Real>(A, s, cl[r], q, u, mp[r], dx3, span);
-    } else {
-      Real p = ph[r];
-      cl[r] = axi_push<GEOM, Real>(A, s, cl[r], q, u, p, mp[r], dx3, span);
-      ph[r] = p;
+      for (int a = 0; a < DIM; ++a) qo[a][r] = qd[a][r];
+      if (r >= cnt || (cl[r] & DEAD_BIT)) continue;
+      OffT<Real> q[3] = {qd[0][r], DIM > 1 ? qd[1][r] : (OffT<Real>)0,
+                         DIM > 2 ? qd[2][r] : (OffT<Real>)0};
+      Real u[3] = {uu[0][r], uu[1][r], uu[2][r]};
+      float span = 0.0f;
+      Real dx3;
+      if (GEOM == 0) {
+        cl[r] = cart_push<DIM, Real, FT>(A, ft, shift, s, cl[r], q, u, mp[r], dx3, span);
+      } else {
+        Real p = ph[r];
+        cl[r] = axi_push<GEOM, Real, FT>(A, ft, s, cl[r], q, u, p, mp[r], dx3, span);
+        ph[r] = p;
+      }
+      d3[r] = dx3;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
+      bmax = fmaxf(bmax, fabsf((float)(qdt * ww[r])) * fmaxf(span, fabsf((float)dx3)));
     }
-    d3[r] = dx3;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
-    bmax = fmaxf(bmax, fabsf((float)(qdt * ww[r])) * fmaxf(span, fabsf((float)dx3)));
-  }
+  };
+  if (use_ft)
+    push_pass(std::true_type{});
+  else
+    push_pass(std::false_type{});
 
   store_n(A.p.cell + p0, cnt, cl);
 #pragma unroll
@@ -464,6 +554,10 @@ __global__ __launch_bounds__(BLOCK) void k_push(StepArgs<Real> A) {
   for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
   if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
   if (!use_tile) return;  // uniform
+
+  // the field copy is done with: the LDS buffer becomes the current tile
+  __syncthreads();
+  for (int x = threadIdx.x; x < 3 * (int)T; x += BLOCK) tile[x] = (Acc)0;
 
   // Fixed-point scale 2^esc of the FP32 tile from the block's largest
   // contribution bound: one particle adds at most B = |q w dt/m| max(span,

@@ -91,20 +91,26 @@ __device__ __forceinline__ Stencil1<Real> stencil1(int i, Real d) {
 __device__ constexpr int kStag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1},
                                         {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
 
+// first-order interpolation from the lattice values around A[base] (row
+// stride s1, plane stride s2): global memory or an LDS tile
 template <int DIM, class Real>
-__device__ __forceinline__ Real gather_one(const Real *__restrict__ A, const GridConst &g, int bx,
-                                           int by, int bz, Real fx, Real fy, Real fz) {
-  const int np0 = g.np[0];
-  const int base = pad_index(g, bx, by, bz, DIM);
+__device__ __forceinline__ Real gather_at(const Real *__restrict__ A, int base, int s1, int s2,
+                                          Real fx, Real fy, Real fz) {
   const Real gx = (Real)1 - fx, gy = (Real)1 - fy;
-  Real v = gy * (gx * A[base] + fx * A[base + 1]) + fy * (gx * A[base + np0] + fx * A[base + np0 + 1]);
+  Real v = gy * (gx * A[base] + fx * A[base + 1]) + fy * (gx * A[base + s1] + fx * A[base + s1 + 1]);
   if (DIM == 3) {
-    const int np01 = np0 * g.np[1];
-    Real v1 = gy * (gx * A[base + np01] + fx * A[base + np01 + 1]) +
-              fy * (gx * A[base + np01 + np0] + fx * A[base + np01 + np0 + 1]);
+    Real v1 = gy * (gx * A[base + s2] + fx * A[base + s2 + 1]) +
+              fy * (gx * A[base + s2 + s1] + fx * A[base + s2 + s1 + 1]);
     v = ((Real)1 - fz) * v + fz * v1;
   }
   return v;
+}
+
+template <int DIM, class Real>
+__device__ __forceinline__ Real gather_one(const Real *__restrict__ A, const GridConst &g, int bx,
+                                           int by, int bz, Real fx, Real fy, Real fz) {
+  return gather_at<DIM, Real>(A, pad_index(g, bx, by, bz, DIM), g.np[0], g.np[0] * g.np[1], fx,
+                              fy, fz);
 }
 
 template <int DIM, class Real>
@@ -120,6 +126,42 @@ __device__ __forceinline__ void interp6(const Real *__restrict__ EB, const GridC
     const Real fy = sy ? st[1].fh : st[1].f0;
     const Real fz = (DIM == 3) ? (sz ? st[2].fh : st[2].f0) : (Real)0;
     F[c] = gather_one<DIM, Real>(EB + c * (int)g.npts, g, bx, by, bz, fx, fy, fz);
+  }
+}
+
+// A block's copy of the six field components over a box of cells (LDS):
+// component c, tile cell (x, y, z) at F[c*T + x + sy*y + sz*z]; o is the box
+// origin in (unwrapped) cell coordinates.
+template <class Real>
+struct FieldTile {
+  const Real *F;
+  int T, sy, sz;
+  int o[3], ts[3];
+};
+
+// every point of the interpolation stencil of cell ib (i-1 ... i+1) inside the tile
+template <int DIM, class Real>
+__device__ __forceinline__ bool fields_in_tile(const FieldTile<Real> &t, const int ib[3]) {
+  bool in = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) in = in && (ib[a] - 1 >= t.o[a]) && (ib[a] + 1 < t.o[a] + t.ts[a]);
+  return in;
+}
+
+// interp6 from the tile; dsh = unwrapped minus stored cell coordinates
+template <int DIM, class Real>
+__device__ __forceinline__ void interp6_tile(const FieldTile<Real> &t, const int dsh[3],
+                                             const Stencil1<Real> st[3], Real F[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int sx = kStag[c][0], sy = kStag[c][1], sz = kStag[c][2];
+    const int bx = (sx ? st[0].bh : st[0].b0) + dsh[0] - t.o[0];
+    const int by = (sy ? st[1].bh : st[1].b0) + dsh[1] - t.o[1];
+    const int bz = (DIM == 3) ? (sz ? st[2].bh : st[2].b0) + dsh[2] - t.o[2] : 0;
+    const Real fx = sx ? st[0].fh : st[0].f0;
+    const Real fy = sy ? st[1].fh : st[1].f0;
+    const Real fz = (DIM == 3) ? (sz ? st[2].fh : st[2].f0) : (Real)0;
+    F[c] = gather_at<DIM, Real>(t.F + c * t.T, bx + t.sy * by + t.sz * bz, t.sy, t.sz, fx, fy, fz);
   }
 }
 
