@@ -95,6 +95,45 @@ __device__ __forceinline__ int div_small(int x, int d, float inv) {
   return q;
 }
 
+// Calls f(x, comp, ix, iy, iz) for every element x = comp*T + ix + s0*iy +
+// s0*s1*iz (T = s0 s1 s2) of an ncomp-component tile, spread over the block.
+// Each thread owns one point of the plane of the first pdims axes (the x
+// row in 2D, the (x, y) plane in 3D) and walks the last axis and the
+// components, so elements need no division; a plane wider than the block
+// falls back to an element loop with divisions.
+template <class F>
+__device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int s1, int s2, F f) {
+  const int T = s0 * s1 * s2;
+  const int P = (pdims == 2) ? s0 * s1 : s0;
+  const int L = (pdims == 2) ? s2 : s1;
+  if (P <= BLOCK) {
+    const int G = BLOCK / P;
+    const int grp = div_small((int)threadIdx.x, P, 1.0f / (float)P);
+    if (grp >= G) return;
+    const int pt = (int)threadIdx.x - grp * P;
+    const int iy0 = div_small(pt, s0, 1.0f / (float)s0);
+    const int ix = pt - iy0 * s0;
+    for (int comp = 0; comp < ncomp; ++comp)
+      for (int w = grp; w < L; w += G) {
+        const int x = comp * T + pt + P * w;
+        if (pdims == 2)
+          f(x, comp, ix, iy0, w);
+        else
+          f(x, comp, ix, w, 0);
+      }
+  } else {
+    const float iT = 1.0f / (float)T, i0f = 1.0f / (float)s0, i01 = 1.0f / (float)(s0 * s1);
+    for (int x = threadIdx.x; x < ncomp * T; x += BLOCK) {
+      const int comp = div_small(x, T, iT);
+      int rem = x - comp * T;
+      const int iz = div_small(rem, s0 * s1, i01);
+      rem -= iz * s0 * s1;
+      const int iy = div_small(rem, s0, i0f);
+      f(x, comp, rem - iy * s0, iy, iz);
+    }
+  }
+}
+
 // block-wide sum of three ints (256 threads)
 __device__ __forceinline__ void block_sum3(int v[3], int *red) {
 #pragma unroll

@@ -421,25 +421,19 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   }
   __syncthreads();
   // flush: one global atomic per nonzero tile value, periodic images resolved
-  const int ts0 = ts[0], ts01 = ts[0] * ts[1];
   const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-  for (int x = threadIdx.x; x < 6 * T; x += BLOCK) {
-    const Acc acc = tile[x];
-    if (acc == (Acc)0) continue;
-    const Real v = (Real)ldexp((double)acc, -esc);
-    const int comp = x / T;
-    int rem = x - comp * T;
-    const int iz = rem / ts01;
-    rem -= iz * ts01;
-    const int iy = rem / ts0;
-    const int ix = rem - iy * ts0;
-    int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
+  tile_for_each(6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+                [&](int x, int comp, int ix, int iy, int iz) {
+                  const Acc acc = tile[x];
+                  if (acc == (Acc)0) return;
+                  const Real v = (Real)ldexp((double)acc, -esc);
+                  int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
-    const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
-                     ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
-    atomic_add_r(A.dEB + gidx, v);
-  }
+                  for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
+                  const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
+                                   ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
+                  atomic_add_r(A.dEB + gidx, v);
+                });
 }
 
 template <class Real>

@@ -471,26 +471,21 @@ void k_push(StepArgs<Real> A) {
     ft.ts[d] = fs[d];
   }
   if (use_ft) {
-    const int Tf = (int)TF, fs0 = fs[0], fs01 = fs[0] * fs[1];
-    const float iT = 1.0f / (float)Tf, i0f = 1.0f / (float)fs0, i01 = 1.0f / (float)fs01;
-    for (int x = threadIdx.x; x < 6 * Tf; x += BLOCK) {
-      const int comp = div_small(x, Tf, iT);
-      int rem = x - comp * Tf;
-      const int iz = div_small(rem, fs01, i01);
-      rem -= iz * fs01;
-      const int iy = div_small(rem, fs0, i0f);
-      const int ix = rem - iy * fs0;
-      int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
-      bool ok = true;
+    const int npts = (int)g.npts;
+    tile_for_each(6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2],
+                  [&](int x, int comp, int ix, int iy, int iz) {
+                    int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
+                    bool ok = true;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        if (GEOM == 0)
-          gi[d] = wrap_periodic(gi[d], g.n[d]);
-        else
-          ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
-      }
-      ftile[x] = ok ? A.EB[comp * (int)g.npts + pad_index(g, gi[0], gi[1], gi[2], DIM)] : (Real)0;
-    }
+                    for (int d = 0; d < DIM; ++d) {
+                      if (GEOM == 0)
+                        gi[d] = wrap_periodic(gi[d], g.n[d]);
+                      else
+                        ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
+                    }
+                    ftile[x] = ok ? A.EB[comp * npts + pad_index(g, gi[0], gi[1], gi[2], DIM)]
+                                  : (Real)0;
+                  });
     __syncthreads();
   }
 
@@ -605,28 +600,21 @@ void k_push(StepArgs<Real> A) {
 
   if (use_tile) {
     __syncthreads();
-    const int Ti = (int)T, ts0 = ts[0], ts01 = ts[0] * ts[1];
-    const float iT = 1.0f / (float)Ti, i0f = 1.0f / (float)ts0, i01 = 1.0f / (float)ts01;
     const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-    for (int x = threadIdx.x; x < 3 * Ti; x += BLOCK) {
-      const Acc acc = tile[x];
-      if (acc == (Acc)0) continue;
-      const Real v = (Real)ldexp((double)acc, -esc);
-      const int comp = div_small(x, Ti, iT);
-      int rem = x - comp * Ti;
-      const int iz = div_small(rem, ts01, i01);
-      rem -= iz * ts01;
-      const int iy = div_small(rem, ts0, i0f);
-      const int ix = rem - iy * ts0;
-      int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
-      if (GEOM == 0) {  // periodic: add straight into the image in the active region
+    tile_for_each(3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+                  [&](int x, int comp, int ix, int iy, int iz) {
+                    const Acc acc = tile[x];
+                    if (acc == (Acc)0) return;
+                    const Real v = (Real)ldexp((double)acc, -esc);
+                    int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
+                    if (GEOM == 0) {  // periodic: add straight into the image
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
-      }
-      const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
-                       ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
-      atomic_add_r(A.J + gidx, v);
-    }
+                      for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
+                    }
+                    const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
+                                     ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
+                    atomic_add_r(A.J + gidx, v);
+                  });
   }
 }
 
