@@ -77,6 +77,11 @@ struct StepArgs {
   int write_prev;
   int deposit;             // 0: move only (adjoint recompute)
   int32_t *stats;          // [0]: blocks, [1]: blocks that deposited with global atomics
+  // a sort's pending reorder (perm == nullptr: none): particle i of a species
+  // is read from src at the species-local index perm[i], and the step writes
+  // the sorted, advanced particles into p
+  const int32_t *perm;
+  PSet<Real> src;
 };
 
 // reverse step: recompute the forward step from the stored state and

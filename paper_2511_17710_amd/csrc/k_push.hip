@@ -357,9 +357,32 @@ void k_push(StepArgs<Real> A) {
 
   int32_t cl[PPT];
   OffT<Real> qd[3][PPT];
-  load_n(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
+  Real uu[3][PPT], ww[PPT], ph[PPT];
+  if (A.perm) {  // first step after a sort: read through the permutation
+    int64_t js[PPT];
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) load_n(A.p.offs[a] + p0, cnt, qd[a], (OffT<Real>)0);
+    for (int r = 0; r < PPT; ++r)
+      js[r] = (r < cnt) ? A.sp.off[s] + (int64_t)A.perm[p0 + r] : A.sp.off[s];
+#pragma unroll
+    for (int r = 0; r < PPT; ++r) {
+      const bool ok = r < cnt;
+      cl[r] = ok ? A.src.cell[js[r]] : (int32_t)DEAD_BIT;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) qd[a][r] = ok ? A.src.offs[a][js[r]] : (OffT<Real>)0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) uu[a][r] = ok ? A.src.u[a][js[r]] : (Real)0;
+      ww[r] = ok ? A.src.w[js[r]] : (Real)0;
+      ph[r] = (ok && GEOM != 0) ? A.src.phi[js[r]] : (Real)0;
+    }
+  } else {
+    load_n(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) load_n(A.p.offs[a] + p0, cnt, qd[a], (OffT<Real>)0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
+    load_n(A.p.w + p0, cnt, ww, (Real)0);
+    if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
+  }
   if (A.write_prev) {
     store_n(A.prev_cell + p0, cnt, cl);
 #pragma unroll
@@ -382,7 +405,18 @@ void k_push(StepArgs<Real> A) {
     }
   }
   block_minmax3(lo, hi, red);
-  if (lo[0] > hi[0]) return;  // no live particle in the chunk (uniform)
+  if (lo[0] > hi[0]) {  // no live particle in the chunk (uniform)
+    if (A.perm) {       // still move the frozen particles into the sorted set
+      store_n(A.p.cell + p0, cnt, cl);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
+      store_n(A.p.w + p0, cnt, ww);
+      if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+    }
+    return;
+  }
   int shift[3] = {0, 0, 0};
   if (GEOM == 0) {
     bool any = false;
@@ -489,11 +523,6 @@ void k_push(StepArgs<Real> A) {
     __syncthreads();
   }
 
-  Real uu[3][PPT], ww[PPT], ph[PPT];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
-  load_n(A.p.w + p0, cnt, ww, (Real)0);
-  if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
 
   const bool use_tile = A.deposit != 0;
   if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
@@ -547,6 +576,7 @@ void k_push(StepArgs<Real> A) {
   for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
+  if (A.perm) store_n(A.p.w + p0, cnt, ww);  // the weights move with the sort
   if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
   if (!use_tile) return;  // uniform
 

@@ -58,6 +58,7 @@ struct pic_ctx {
   int32_t ckpt_K = -1, ckpt_m = -1;  // last pic_forward_checkpointed
   int64_t ckpt_step0 = 0;
   std::vector<int32_t> ckpt_sorts;  // steps n of that run that began with a sort
+  bool perm_pending = false;        // a sort's reorder left to the next step
   bool timing = false;
   struct Ev {
     hipEvent_t a, b;
@@ -170,8 +171,12 @@ void ev_end(pic_ctx *c, int idx) {
   if (idx >= 0) (void)hipEventRecord(c->events[idx].b, c->stream);
 }
 
+// The stable per-cell sort.  materialize: reorder every array now (gather
+// into the other set); else the permutation stays pending and the next step
+// reads through it while it writes the sorted, advanced particles into the
+// other set (one pass over the particle data instead of two).
 template <class Real>
-pic_status do_sort(pic_ctx *c) {
+pic_status do_sort(pic_ctx *c, bool materialize) {
   const int ev = ev_begin(c, 1);
   SortScratch S{};
   for (int a = 0; a < 2; ++a) {
@@ -189,12 +194,35 @@ pic_status do_sort(pic_ctx *c) {
     if (n == 0) continue;
     hipError_t e = launch_sort_species(c->g, src.cell + o, n, S, perm + o, c->keybits, c->stream);
     if (e != hipSuccess) return hipchk(c, e, "sort");
-    e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o, c->stream);
-    if (e != hipSuccess) return hipchk(c, e, "gather");
+    if (materialize) {
+      e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o, c->stream);
+      if (e != hipSuccess) return hipchk(c, e, "gather");
+    }
   }
   // species with no particles keep nothing worth copying; flip the set
-  c->active ^= 1;
+  if (materialize)
+    c->active ^= 1;
+  else
+    c->perm_pending = true;
   ev_end(c, ev);
+  return PIC_OK;
+}
+
+// apply a pending sort's reorder (after a failed step; entry points that
+// touch the particle sets call this first)
+template <class Real>
+pic_status settle(pic_ctx *c) {
+  if (!c->perm_pending) return PIC_OK;
+  const int32_t *perm = reinterpret_cast<const int32_t *>(c->scratch + c->s_perm);
+  const PSet<Real> src = pset_of<Real>(c, c->active), dst = pset_of<Real>(c, c->active ^ 1);
+  for (int s = 0; s < c->nspec; ++s) {
+    const int64_t n = (int64_t)c->cnt[s], o = (int64_t)c->off[s];
+    hipError_t e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o,
+                                       c->stream);
+    if (e != hipSuccess) return hipchk(c, e, "gather");
+  }
+  c->active ^= 1;
+  c->perm_pending = false;
   return PIC_OK;
 }
 
@@ -204,6 +232,12 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   a.g = c->g;
   a.sp = species_table(c, dt, PUSH_CHUNK);
   a.p = pset_of<Real>(c, c->active);
+  a.perm = nullptr;
+  if (c->perm_pending) {  // read through the pending sort, write the other set
+    a.perm = reinterpret_cast<const int32_t *>(c->scratch + c->s_perm);
+    a.src = a.p;
+    a.p = pset_of<Real>(c, c->active ^ 1);
+  }
   a.prev_cell = reinterpret_cast<int32_t *>(c->prev + c->p_cell);
   for (int d = 0; d < 3; ++d)
     a.prev_offs[d] = c->p_offs[d] == NONE ? nullptr : reinterpret_cast<OffT<Real> *>(c->prev + c->p_offs[d]);
@@ -220,6 +254,10 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   e = launch_push_deposit<Real>(a, c->stream);
   ev_end(c, ev);
   if (e != hipSuccess) return hipchk(c, e, "push_deposit");
+  if (a.perm) {
+    c->active ^= 1;
+    c->perm_pending = false;
+  }
   if (dep) e = launch_fold_ghosts<Real>(c->g, a.J, 3, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "fold J");
   return PIC_OK;
@@ -229,7 +267,7 @@ template <class Real>
 pic_status run_steps(pic_ctx *c, double dt, int32_t n, bool allow_sort) {
   for (int32_t s = 0; s < n; ++s) {
     if (allow_sort && c->d.sort_every > 0 && c->step % c->d.sort_every == 0) {
-      pic_status st = do_sort<Real>(c);
+      pic_status st = do_sort<Real>(c, false);
       if (st != PIC_OK) return st;
     }
     pic_status st = do_step<Real>(c, dt, s == n - 1);
@@ -329,7 +367,7 @@ pic_status fwd_ckpt(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws) {
     }
     if (c->d.sort_every > 0 && c->step % c->d.sort_every == 0) {
       if (c->ckpt_sorts.size() >= L.nperm) return fail(c, PIC_E_STATE, "sort count");
-      pic_status st = do_sort<Real>(c);
+      pic_status st = do_sort<Real>(c, false);
       if (st != PIC_OK) return st;
       hipError_t e = hipMemcpyAsync(ws + L.perm0 + c->ckpt_sorts.size() * L.perm_bytes, perm,
                                     c->capacity * 4, hipMemcpyDeviceToDevice, c->stream);
@@ -770,6 +808,10 @@ pic_status pic_particles_load(pic_ctx *c, int32_t s, uint64_t n, const int32_t *
   if (n > c->cap[s]) return fail(c, PIC_E_CAPACITY, "%llu particles exceed species capacity %llu",
                                  (unsigned long long)n, (unsigned long long)c->cap[s]);
   if (n > 0 && (!cell || !offs || !u || !w)) return fail(c, PIC_E_ARG, "null particle array");
+  {
+    const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+    if (st != PIC_OK) return st;
+  }
   const GridConst &g = c->g;
   const bool axi = g.geom != 0;
   if (n > 0 && axi && !phi) return fail(c, PIC_E_ARG, "phi required on (quasi-)spherical grids");
@@ -839,7 +881,9 @@ pic_status pic_particles_load(pic_ctx *c, int32_t s, uint64_t n, const int32_t *
 pic_status pic_sort(pic_ctx *c) {
   if (!c) return PIC_E_ARG;
   if (!c->bound) return fail(c, PIC_E_STATE, "sort before bind_buffers");
-  return c->eb == 8 ? do_sort<double>(c) : do_sort<float>(c);
+  pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
+  return c->eb == 8 ? do_sort<double>(c, true) : do_sort<float>(c, true);
 }
 
 pic_status pic_push_deposit(pic_ctx *c, double dt, int32_t n_steps) {
@@ -848,6 +892,8 @@ pic_status pic_push_deposit(pic_ctx *c, double dt, int32_t n_steps) {
   if (!(dt > 0) || !isfin(dt) || n_steps < 0) return fail(c, PIC_E_ARG, "bad dt or n_steps");
   if (dt > c->dx_min)
     return fail(c, PIC_E_ARG, "dt %g exceeds the CFL limit %g (Courant number 1)", dt, c->dx_min);
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
   return c->eb == 8 ? run_steps<double>(c, dt, n_steps, true) : run_steps<float>(c, dt, n_steps, true);
 }
 
@@ -873,6 +919,8 @@ pic_status pic_particles_get(const pic_ctx *c, int32_t s, pic_particle_view *v) 
   if (!c || !v) return PIC_E_ARG;
   if (!c->bound) return fail(c, PIC_E_STATE, "not bound");
   if (s < 0 || s >= c->nspec) return fail(c, PIC_E_ARG, "bad species %d", s);
+  if (c->perm_pending)
+    return fail(c, PIC_E_STATE, "a failed step left a sort unapplied: call pic_sort or push again");
   const uint64_t n = c->cnt[s];
   if (v->n < n) return fail(c, PIC_E_CAPACITY, "view holds %llu < %llu particles",
                            (unsigned long long)v->n, (unsigned long long)n);
@@ -1021,6 +1069,8 @@ pic_status pic_forward_checkpointed(pic_ctx *c, double dt, int32_t K, int32_t m,
   if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "forward before bind/fields_set");
   if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (!(dt > 0) || dt > c->dx_min) return fail(c, PIC_E_ARG, "bad dt");
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
   return c->eb == 8 ? fwd_ckpt<double>(c, dt, K, m, static_cast<char *>(ws))
                     : fwd_ckpt<float>(c, dt, K, m, static_cast<char *>(ws));
 }
@@ -1032,6 +1082,8 @@ pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, c
   if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (c->ckpt_K != K || c->ckpt_m != m)
     return fail(c, PIC_E_STATE, "backward(K=%d, m=%d) without a matching forward_checkpointed", K, m);
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
   return c->eb == 8 ? bwd<double>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0)
                     : bwd<float>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0);
 }
