@@ -234,7 +234,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
       const uint32_t key = sk[e];
       const uint32_t dg = (key >> shift) & (RADIX - 1);
       const int64_t dst = (int64_t)cnt[0][dg] + (e - dstart[dg]);
-      kout[dst] = key;
+      if (kout) kout[dst] = key;  // the last pass keeps only the permutation
       vout[dst] = sv[e];
     }
   }
@@ -264,7 +264,8 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
                        S.bsum);
     int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks,
-                       S.keys[dst], vdst, n, shift, S.hist, ntiles);
+                       (ps == passes - 1) ? nullptr : S.keys[dst], vdst, n, shift, S.hist,
+                       ntiles);
   }
   return hipGetLastError();
 }
