@@ -2,13 +2,16 @@
 // (arXiv 2511.17710, Sec. 2.3 steps 3-8), one launch for all species.
 //
 // A block owns CHUNK consecutive particles of one species (4 per thread,
-// loaded with 16-byte vector accesses).  Particles are kept in brick order by
-// the per-cell sort, so the chunk's cells form a compact box: the block
-// privatises the current of that box (plus the stencil halo) in LDS,
-// accumulates with LDS atomics, and flushes every nonzero tile value with one
-// global atomic.  When the box outgrows the tile (particles drifted far since
-// the last sort, or wrapped across a periodic boundary) the block deposits
-// with global atomics instead; both paths give the same sums.
+// loaded with 16-byte vector accesses, or through the permutation of a sort
+// on the step that follows it).  Particles are kept in brick order by the
+// per-cell sort, so the chunk's cells form a compact box.  One LDS buffer
+// serves in turn as the block's copy of the fields over that box (FP32, when
+// it fits) for the push pass, and as the block's current tile over the box
+// (plus the stencil halo) for the deposit pass: exact 64-bit fixed-point
+// accumulation in FP32 builds, double in FP64 builds, flushed with one global
+// atomic per nonzero value.  When the box outgrows the tile (particles
+// drifted far since the last sort) the particles whose stencil leaves the
+// tile read the fields and deposit in global memory; the sums are the same.
 #include <type_traits>
 
 #include "block_util.h"
