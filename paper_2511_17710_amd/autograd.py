@@ -8,7 +8,10 @@ last step and the final four-velocities.  Its backward runs the library's
 hand-written adjoint kernels with checkpoints every m steps and returns
 dL/dEB (periodic ghost contributions added into their images) and dL/du0.
 Positions are inputs of the map taken from the context; they are not
-differentiated, and no sort happens inside the K steps.
+differentiated.  The K steps run exactly as ctx.push_deposit would run them,
+sorts of the context's cadence included: u_K is in the particle order at
+step K (ctx.checkpointed_order() gives each slot's step-0 slot), u0 and
+dL/du0 in the order at step 0.
 """
 import torch
 
