@@ -89,7 +89,7 @@ def run_gpu(wl, prec, steps, warmup, log):
                push_ms_avg=tm["push_ms"] / max(tm["push_launches"], 1),
                push_launches=tm["push_launches"], sort_ms_total=tm["sort_ms"],
                sort_calls=tm["sort_calls"],
-               tile_fallback_frac=round(tm["push_fallback_blocks"] / max(tm["push_blocks"], 1), 5))
+               global_deposits_per_block=round(tm["push_global_particles"] / max(tm["push_blocks"], 1), 5))
     log(f"[bench] {prec}: {res}")
     del ctx
     torch.cuda.empty_cache()

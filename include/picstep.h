@@ -246,7 +246,8 @@ typedef struct {
   int64_t adjoint_launches;
   double adjoint_ms;
   int64_t push_blocks;           /* blocks of the fused kernel with live particles */
-  int64_t push_fallback_blocks;  /* of which deposited with global atomics (box > LDS tile) */
+  int64_t push_global_particles; /* particles whose stencil left the LDS tile, deposited with
+                                    global atomics */
 } pic_timing;
 pic_status pic_timing_enable(pic_ctx *ctx, int32_t enable);
 pic_status pic_timing_read(pic_ctx *ctx, pic_timing *out);

@@ -1052,7 +1052,7 @@ pic_status pic_timing_read(pic_ctx *c, pic_timing *out) {
     err = hipMemcpyAsync(st, c->scratch + c->s_stats, 16, hipMemcpyDeviceToHost, c->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
     out->push_blocks = st[0];
-    out->push_fallback_blocks = st[1];
+    out->push_global_particles = st[1];
     if (err == hipSuccess) err = hipMemsetAsync(c->scratch + c->s_stats, 0, 16, c->stream);
   }
   return hipchk(c, err, "timing_read");

@@ -53,7 +53,7 @@ class Layout(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("push_launches", C.c_int64), ("push_ms", C.c_double), ("sort_calls", C.c_int64),
                 ("sort_ms", C.c_double), ("adjoint_launches", C.c_int64), ("adjoint_ms", C.c_double),
-                ("push_blocks", C.c_int64), ("push_fallback_blocks", C.c_int64)]
+                ("push_blocks", C.c_int64), ("push_global_particles", C.c_int64)]
 
 
 class ParticleView(C.Structure):
