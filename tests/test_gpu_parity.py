@@ -116,6 +116,35 @@ def test_curvilinear_multistep_with_sorts_and_exits(prec):
         assert U.rel_l2(Jg, Jref) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sort_reorder_fused_into_the_step(prec):
+    """The reorder of a sort rides on the next step (the push reads through
+    the permutation); an explicit sort reorders the arrays at once.  Both
+    must leave identical particles."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[parity] fused reorder {prec}", flush=True)
+    wl = W.curvilinear("qsph", 32, 16, 3.0, 0.3, ppc=3, theta=2.0, density_power=0, steps=3,
+                       seed=38, shuffle=True)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    a = P.from_workload(wl, prec=prec, sort_every=1)
+    b = P.from_workload(wl, prec=prec, sort_every=0)
+    dt = a.timestep_from_cfl(wl.cfl)
+    a.push_deposit(dt, 3)
+    for _ in range(3):
+        b.sort()
+        b.push_deposit(dt, 1)
+    torch.cuda.synchronize()
+    for s in range(len(wl.species)):
+        qa, qb = a.particles_get(s), b.particles_get(s)
+        for key in ("perm", "cell", "offs", "u", "w", "phi", "alive", "cell_prev", "offs_prev"):
+            np.testing.assert_array_equal(qa[key], qb[key], err_msg=key)
+    ja, jb = a.current_host().astype(np.float64), b.current_host().astype(np.float64)
+    assert U.rel_l2(ja, jb) < (1e-13 if prec == "f64" else 1e-6)
+
+
 def test_edge_cases_empty_ragged_single_cell():
     """A species with no particles, a ragged particle count, and every particle
     of a species in one cell (one huge sort bucket)."""
