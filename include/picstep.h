@@ -294,6 +294,33 @@ pic_status pic_backward(pic_ctx *ctx, double dt, int32_t K, int32_t m, void *wor
  * a completed forward. */
 pic_status pic_checkpointed_order(const pic_ctx *ctx, const void *workspace, int32_t *dst);
 
+/* ---- lower-level adjoint pieces, for callers with their own checkpoint
+ * schedule.  A checkpoint is the particle state (cell, offsets, u, w, phi)
+ * of the whole capacity, pic_sizes.checkpoint_bytes in the device buffer
+ * `slot`; the step counter is not part of it.  Asynchronous. */
+pic_status pic_checkpoint_save(pic_ctx *ctx, void *slot);
+pic_status pic_checkpoint_load(pic_ctx *ctx, const void *slot);
+
+typedef struct {
+  void *lam_u;     /* device [3][capacity] real: in dL/du after the step, out dL/du before */
+  void *lam_offs;  /* device [3][capacity] real: likewise for the in-cell offsets (rows of
+                      unused dimensions are left untouched) */
+  void *dEB;       /* device [6][npts] real: the step's dL/d(fields) is added, periodic
+                      ghost contributions folded into their images */
+  void *lamJ_work; /* device [3][npts] real scratch, used when lamJ is given */
+} pic_adjoint_buffers;
+
+/* Reverse of one particle step (Cartesian grids) from the current particle
+ * state, the state before that step (e.g. just restored with
+ * pic_checkpoint_load): lamJ (device [3][npts] real, dL/dJ of this step, may
+ * be NULL) is gathered through the step's zig-zag, the adjoints of u and of
+ * the offsets are carried back through the move and the Boris push, and the
+ * interpolation's adjoint is scattered into dEB.  A sort that began the step
+ * is not reversed here (pic_backward handles sorts; with sort_every = 0 there
+ * are none).  The particle state is left unchanged.  Asynchronous. */
+pic_status pic_adjoint_step(pic_ctx *ctx, double dt, const void *lamJ,
+                            const pic_adjoint_buffers *io);
+
 /* Message of the last failing call on this context (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);
 

@@ -522,6 +522,39 @@ double cfl_length(const GridConst &g) {
 }  // namespace
 
 
+template <class Real>
+pic_status adjoint_one(pic_ctx *c, double dt, const void *lamJ, const pic_adjoint_buffers *io) {
+  const GridConst &g = c->g;
+  const uint64_t cap = c->capacity;
+  AdjArgs<Real> A{};
+  A.g = g;
+  A.sp = species_table(c, dt, BLOCK);
+  A.p = pset_of<Real>(c, c->active);
+  A.EB = reinterpret_cast<const Real *>(c->fields);
+  A.dEB = static_cast<Real *>(io->dEB);
+  A.dt = dt;
+  for (int a = 0; a < 3; ++a) {
+    A.lam_u[a] = static_cast<Real *>(io->lam_u) + a * cap;
+    A.lam_d[a] = static_cast<Real *>(io->lam_offs) + a * cap;
+  }
+  A.lam_phi = nullptr;
+  A.lamJ = nullptr;
+  hipError_t e = hipSuccess;
+  if (lamJ) {  // a deposit into a periodic ghost ends up in its image: gather from there
+    Real *w = static_cast<Real *>(io->lamJ_work);
+    e = hipMemcpyAsync(w, lamJ, 3ull * g.npts * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_ghosts<Real>(g, w, 3, c->stream);
+    A.lamJ = w;
+  }
+  if (e == hipSuccess) {
+    const int ev = ev_begin(c, 2);
+    e = launch_adjoint_step<Real>(A, c->stream);
+    ev_end(c, ev);
+  }
+  if (e == hipSuccess) e = launch_fold_ghosts<Real>(g, A.dEB, 6, c->stream);
+  return hipchk(c, e, "adjoint_step");
+}
+
 extern "C" {
 
 pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
@@ -1112,6 +1145,39 @@ pic_status pic_checkpointed_order(const pic_ctx *c, const void *ws, int32_t *dst
   }
   std::memcpy(dst, order.data(), n * 4);
   return PIC_OK;
+}
+
+pic_status pic_checkpoint_save(pic_ctx *c, void *slot) {
+  if (!c || !slot) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "checkpoint_save before bind_buffers");
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
+  hipError_t e = c->eb == 8
+      ? copy_state<double>(c, slot_pset<double>(c, static_cast<char *>(slot)), pset_of<double>(c, c->active))
+      : copy_state<float>(c, slot_pset<float>(c, static_cast<char *>(slot)), pset_of<float>(c, c->active));
+  return hipchk(c, e, "checkpoint_save");
+}
+
+pic_status pic_checkpoint_load(pic_ctx *c, const void *slot) {
+  if (!c || !slot) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "checkpoint_load before bind_buffers");
+  c->perm_pending = false;  // the loaded state replaces the sets' contents
+  char *sl = const_cast<char *>(static_cast<const char *>(slot));
+  hipError_t e = c->eb == 8
+      ? copy_state<double>(c, pset_of<double>(c, c->active), slot_pset<double>(c, sl))
+      : copy_state<float>(c, pset_of<float>(c, c->active), slot_pset<float>(c, sl));
+  return hipchk(c, e, "checkpoint_load");
+}
+
+pic_status pic_adjoint_step(pic_ctx *c, double dt, const void *lamJ, const pic_adjoint_buffers *io) {
+  if (!c || !io || !io->lam_u || !io->lam_offs || !io->dEB || (lamJ && !io->lamJ_work))
+    return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "adjoint_step before bind/fields_set");
+  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
+  if (!(dt > 0) || dt > c->dx_min) return fail(c, PIC_E_ARG, "bad dt");
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
+  return c->eb == 8 ? adjoint_one<double>(c, dt, lamJ, io) : adjoint_one<float>(c, dt, lamJ, io);
 }
 
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -56,6 +56,11 @@ class Timing(C.Structure):
                 ("push_blocks", C.c_int64), ("push_global_particles", C.c_int64)]
 
 
+class AdjointBuffers(C.Structure):
+    _fields_ = [("lam_u", C.c_void_p), ("lam_offs", C.c_void_p), ("dEB", C.c_void_p),
+                ("lamJ_work", C.c_void_p)]
+
+
 class ParticleView(C.Structure):
     _fields_ = [("n", C.c_uint64), ("cell", C.POINTER(C.c_int32)), ("offs", C.POINTER(C.c_double)),
                 ("u", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
@@ -98,6 +103,9 @@ def lib():
             "pic_forward_checkpointed": [vp, dbl, i32, i32, vp],
             "pic_backward": [vp, dbl, i32, i32, vp, vp, vp, vp, vp],
             "pic_checkpointed_order": [vp, vp, vp],
+            "pic_checkpoint_save": [vp, vp],
+            "pic_checkpoint_load": [vp, vp],
+            "pic_adjoint_step": [vp, dbl, vp, C.POINTER(AdjointBuffers)],
             "pic_last_error": [vp],
             "pic_timing_enable": [vp, i32],
             "pic_timing_read": [vp, C.POINTER(Timing)],
@@ -295,6 +303,37 @@ class Context:
                     "backward")
         torch.cuda.current_stream(self.device).synchronize()
         return dEB, du0
+
+    # -------------------------------------------------------------- low-level adjoint
+    def checkpoint_slot(self):
+        """A torch device buffer for one particle-state checkpoint."""
+        return torch.empty(max(int(self.sizes().checkpoint_bytes), 256), dtype=torch.uint8,
+                           device=self.device)
+
+    def checkpoint_save(self, slot):
+        self._check(lib().pic_checkpoint_save(self.h, C.c_void_p(slot.data_ptr())),
+                    "checkpoint_save")
+
+    def checkpoint_load(self, slot):
+        self._check(lib().pic_checkpoint_load(self.h, C.c_void_p(slot.data_ptr())),
+                    "checkpoint_load")
+
+    def adjoint_step(self, dt, lam_u, lam_offs, dEB, lamJ=None, work=None):
+        """Reverse of one step from the current state: lam_u, lam_offs
+        ([3, capacity]) are updated in place, dEB ([6, np3, np2, np1]) is
+        accumulated; lamJ ([3, np3, np2, np1]) needs a work buffer of the same
+        shape."""
+        b = AdjointBuffers()
+        b.lam_u = lam_u.data_ptr()
+        b.lam_offs = lam_offs.data_ptr()
+        b.dEB = dEB.data_ptr()
+        pJ = None
+        if lamJ is not None:
+            if work is None:
+                work = torch.empty_like(lamJ)
+            b.lamJ_work = work.data_ptr()
+            pJ = C.c_void_p(lamJ.data_ptr())
+        self._check(lib().pic_adjoint_step(self.h, float(dt), pJ, C.byref(b)), "adjoint_step")
 
     def checkpointed_order(self):
         """int32 [capacity]: for each particle slot at step K of the last

@@ -134,6 +134,48 @@ def test_adjoint_with_sorts_inside_the_map(dim, prec):
         np.testing.assert_array_equal(q["cell"][:, :dim], wl.species[s]["cell"][:, :dim])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_manual_checkpoints_and_adjoint_steps(prec):
+    """pic_checkpoint_save / pic_checkpoint_load / pic_adjoint_step driven by
+    the caller reproduce pic_forward_checkpointed + pic_backward."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[adjoint] manual checkpoints {prec}", flush=True)
+    K = 4
+    wl = _case(3, K, 47)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    lamJ, lam_u = _weights(wl, 12)
+    dEB_ref, du_ref, _, _, dt = _gpu_grad(wl, prec, K, 2, lamJ, lam_u)
+    ctx = P.from_workload(wl, prec=prec, sort_every=0)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    L = ctx.layout()
+    slots = [ctx.checkpoint_slot() for _ in range(K)]
+    for n in range(K):
+        ctx.checkpoint_save(slots[n])
+        ctx.push_deposit(dt, 1)
+    lu = torch.zeros((3, L.capacity), dtype=dtype, device="cuda")
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        lu[:, o:o + lam.shape[0]] = torch.from_numpy(lam.T.copy()).to(dtype=dtype, device="cuda")
+    ld = torch.zeros_like(lu)
+    dEB = torch.zeros((6,) + ctx.padded_shape(), dtype=dtype, device="cuda")
+    lJ = torch.from_numpy(lamJ).to(dtype=dtype, device="cuda")
+    for n in range(K - 1, -1, -1):
+        ctx.checkpoint_load(slots[n])
+        ctx.adjoint_step(dt, lu, ld, dEB, lamJ=lJ if n == K - 1 else None)
+    torch.cuda.synchronize()
+    du0 = lu.double().cpu().numpy()
+    du = [du0[:, L.species_offset[s]:L.species_offset[s] + lam.shape[0]].T
+          for s, lam in enumerate(lam_u)]
+    eE = U.rel_l2(dEB.double().cpu().numpy(), dEB_ref)
+    eu = U.rel_l2(np.concatenate(du), np.concatenate(du_ref))
+    print(f"  dEB {eE:.2e} du0 {eu:.2e}", flush=True)
+    assert eu == 0.0 or eu < 1e-14
+    assert eE < (1e-13 if prec == "f64" else 1e-6)
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     """Recomputing from checkpoints reproduces the stored trajectory exactly:
     du0 is bitwise equal for m = K and m = 1; dEB agrees up to the order of
