@@ -129,6 +129,7 @@ typedef struct {
   int32_t active_set;      /* which of the two bound sets holds the current state */
   int32_t shift2, shift3;  /* cell packing */
   uint64_t prev_cell, prev_offs[3]; /* byte offsets inside the prev buffer */
+  uint64_t id;             /* int32 particle id: its index in the pic_particles_load call */
 } pic_layout;
 
 /* Host view of one species for pic_particles_get: arrays of n (x3 for cell,
@@ -144,6 +145,7 @@ typedef struct {
   int32_t *cell_prev;  /* n x 3, positions before the last pushed step */
   double *offs_prev;   /* n x 3 */
   int32_t *perm;       /* n, permutation applied by the last sort (new i <- old perm[i]) */
+  int32_t *id;         /* n, each particle's index in its pic_particles_load call */
 } pic_particle_view;
 
 /* ---- context and setup (Sec. 2.4, Sec. 3.1) ---- */

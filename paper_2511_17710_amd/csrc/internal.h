@@ -53,6 +53,7 @@ struct PSet {  // SoA of one particle set (device pointers)
   Real *u[3];
   Real *w;
   Real *phi;
+  int32_t *id;  // loaded index within the species, carried through every sort
 };
 
 struct SpeciesTable {

@@ -361,7 +361,9 @@ void k_push(StepArgs<Real> A) {
   int32_t cl[PPT];
   OffT<Real> qd[3][PPT];
   Real uu[3][PPT], ww[PPT], ph[PPT];
-  if (A.perm) {  // first step after a sort: read through the permutation
+  if (A.perm) {  // first step after a sort: read through the permutation; the ids
+                 // move to the sorted set here as well
+    int32_t idv[PPT];
     int64_t js[PPT];
 #pragma unroll
     for (int r = 0; r < PPT; ++r)
@@ -376,7 +378,9 @@ void k_push(StepArgs<Real> A) {
       for (int a = 0; a < 3; ++a) uu[a][r] = ok ? A.src.u[a][js[r]] : (Real)0;
       ww[r] = ok ? A.src.w[js[r]] : (Real)0;
       ph[r] = (ok && GEOM != 0) ? A.src.phi[js[r]] : (Real)0;
+      idv[r] = ok ? A.src.id[js[r]] : 0;
     }
+    store_n(A.p.id + p0, cnt, idv);
   } else {
     load_n(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
 #pragma unroll

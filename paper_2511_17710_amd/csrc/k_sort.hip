@@ -306,6 +306,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_gather(PSet<Real> src, PSet<Re
   for (int a = 0; a < 3; ++a) gather_array(src.u[a], dst.u[a], off, i, pj);
   gather_array(src.w, dst.w, off, i, pj);
   if (has_phi) gather_array(src.phi, dst.phi, off, i, pj);
+  gather_array(src.id, dst.id, off, i, pj);
 }
 
 template <class Real>

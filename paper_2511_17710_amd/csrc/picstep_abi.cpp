@@ -38,7 +38,7 @@ struct pic_ctx {
   uint64_t cap[MAXSP]{}, off[MAXSP]{}, cnt[MAXSP]{};
   uint64_t capacity = 0;  // elements per particle array
   // particle set layout (byte offsets)
-  uint64_t o_cell = 0, o_offs[3]{NONE, NONE, NONE}, o_u[3]{}, o_w = 0, o_phi = NONE;
+  uint64_t o_cell = 0, o_offs[3]{NONE, NONE, NONE}, o_u[3]{}, o_w = 0, o_phi = NONE, o_id = 0;
   uint64_t set_bytes = 0;
   uint64_t p_cell = 0, p_offs[3]{NONE, NONE, NONE}, prev_bytes = 0;
   // scratch layout
@@ -135,6 +135,7 @@ PSet<Real> pset_of(const pic_ctx *c, int which) {
   }
   p.w = reinterpret_cast<Real *>(b + c->o_w);
   p.phi = c->o_phi == NONE ? nullptr : reinterpret_cast<Real *>(b + c->o_phi);
+  p.id = reinterpret_cast<int32_t *>(b + c->o_id);
   return p;
 }
 
@@ -328,7 +329,11 @@ PSet<Real> slot_pset(const pic_ctx *c, char *slot) {
   p.w = reinterpret_cast<Real *>(slot + o);
   o += ab;
   p.phi = nullptr;
-  if (c->g.geom != 0) p.phi = reinterpret_cast<Real *>(slot + o);
+  if (c->g.geom != 0) {
+    p.phi = reinterpret_cast<Real *>(slot + o);
+    o += ab;
+  }
+  p.id = reinterpret_cast<int32_t *>(slot + o);
   return p;
 }
 
@@ -342,6 +347,8 @@ hipError_t copy_state(const pic_ctx *c, const PSet<Real> &dst, const PSet<Real> 
     e = hipMemcpyAsync(dst.u[a], src.u[a], n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dst.w, src.w, n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst.id, src.id, n * 4, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && c->g.geom != 0)
     e = hipMemcpyAsync(dst.phi, src.phi, n * sizeof(Real), hipMemcpyDeviceToDevice, c->stream);
   return e;
@@ -657,6 +664,8 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
     c->o_phi = o;
     o += ab;
   }
+  c->o_id = o;
+  o += ai;
   c->set_bytes = o;
   o = 0;
   c->p_cell = o;
@@ -683,8 +692,8 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   c->s_stats = o;
   o += ALIGN;
   c->scratch_bytes = o;
-  // checkpoint: cell, offsets, u, w, phi
-  c->ckpt_bytes = ai + (uint64_t)d.dim * ab + 4 * ab + (d.geom != PIC_CART ? ab : 0);
+  // checkpoint: cell, offsets, u, w, phi, id
+  c->ckpt_bytes = 2 * ai + (uint64_t)d.dim * ab + 4 * ab + (d.geom != PIC_CART ? ab : 0);
   c->dx_min = cfl_length(g);
   *out = c;
   return PIC_OK;
@@ -903,6 +912,12 @@ pic_status pic_particles_load(pic_ctx *c, int32_t s, uint64_t n, const int32_t *
     for (int a = 0; a < 3 && e == hipSuccess; ++a) e = put(c->o_u[a], u, 3, a);
     if (e == hipSuccess) e = put(c->o_w, w, 1, 0);
     if (e == hipSuccess && axi) e = put(c->o_phi, phi, 1, 0);
+    if (e == hipSuccess) {
+      std::vector<int32_t> ids(n);
+      for (uint64_t p = 0; p < n; ++p) ids[p] = (int32_t)p;
+      e = hipMemcpyAsync(base + c->o_id + o * 4, ids.data(), n * 4, hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hipchk(c, e, "particles_load");
@@ -1017,6 +1032,10 @@ pic_status pic_particles_get(const pic_ctx *c, int32_t s, pic_particle_view *v) 
     e = hipMemcpyAsync(v->perm, c->scratch + c->s_perm + o * 4, n * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   }
+  if (v->id && e == hipSuccess) {
+    e = hipMemcpyAsync(v->id, base + c->o_id + o * 4, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
   return hipchk(c, e, "particles_get");
 }
 
@@ -1031,6 +1050,7 @@ pic_status pic_particle_layout(const pic_ctx *c, pic_layout *L) {
   }
   L->w = c->o_w;
   L->phi = c->o_phi;
+  L->id = c->o_id;
   L->capacity = c->capacity;
   for (int s = 0; s < MAXSP; ++s) {
     L->species_offset[s] = s < c->nspec ? c->off[s] : 0;

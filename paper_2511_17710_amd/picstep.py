@@ -47,7 +47,7 @@ class Layout(C.Structure):
                 ("species_offset", C.c_uint64 * MAXSP), ("species_capacity", C.c_uint64 * MAXSP),
                 ("species_count", C.c_uint64 * MAXSP), ("nspecies", C.c_int32),
                 ("active_set", C.c_int32), ("shift2", C.c_int32), ("shift3", C.c_int32),
-                ("prev_cell", C.c_uint64), ("prev_offs", C.c_uint64 * 3)]
+                ("prev_cell", C.c_uint64), ("prev_offs", C.c_uint64 * 3), ("id", C.c_uint64)]
 
 
 class Timing(C.Structure):
@@ -66,7 +66,7 @@ class ParticleView(C.Structure):
                 ("u", C.POINTER(C.c_double)), ("w", C.POINTER(C.c_double)),
                 ("phi", C.POINTER(C.c_double)), ("alive", C.POINTER(C.c_int32)),
                 ("cell_prev", C.POINTER(C.c_int32)), ("offs_prev", C.POINTER(C.c_double)),
-                ("perm", C.POINTER(C.c_int32))]
+                ("perm", C.POINTER(C.c_int32)), ("id", C.POINTER(C.c_int32))]
 
 
 _LIB = None
@@ -376,7 +376,8 @@ class Context:
         out = dict(cell=self._view(buf, L.cell, cap, torch.int32),
                    u=[self._view(buf, L.u[a], cap, self.dtype) for a in range(3)],
                    offs=[self._view(buf, L.offs[a], cap, self.dtype) for a in range(self.dim)],
-                   w=self._view(buf, L.w, cap, self.dtype))
+                   w=self._view(buf, L.w, cap, self.dtype),
+                   id=self._view(buf, L.id, cap, torch.int32))
         if L.phi != none:
             out["phi"] = self._view(buf, L.phi, cap, self.dtype)
         return out
@@ -387,10 +388,10 @@ class Context:
         out = dict(cell=np.zeros((n, 3), np.int32), offs=np.zeros((n, 3)), u=np.zeros((n, 3)),
                    w=np.zeros(n), phi=np.zeros(n) if self.geom != 0 else None,
                    alive=np.zeros(n, np.int32), cell_prev=np.zeros((n, 3), np.int32),
-                   offs_prev=np.zeros((n, 3)), perm=np.zeros(n, np.int32))
+                   offs_prev=np.zeros((n, 3)), perm=np.zeros(n, np.int32), id=np.zeros(n, np.int32))
         v = ParticleView()
         v.n = n
-        for k in ("cell", "alive", "cell_prev", "perm"):
+        for k in ("cell", "alive", "cell_prev", "perm", "id"):
             setattr(v, k, out[k].ctypes.data_as(C.POINTER(C.c_int32)))
         for k in ("offs", "u", "w", "offs_prev"):
             setattr(v, k, out[k].ctypes.data_as(C.POINTER(C.c_double)))

@@ -45,8 +45,8 @@ def test_ctypes_structs_match_header():
 int main(void){
   printf("%zu %zu %zu %zu %zu\n", sizeof(pic_grid_desc), sizeof(pic_sizes), sizeof(pic_buffers),
          sizeof(pic_layout), sizeof(pic_particle_view));
-  printf("%zu %zu %zu\n", offsetof(pic_grid_desc, max_particles), offsetof(pic_layout, nspecies),
-         offsetof(pic_layout, prev_cell));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(pic_grid_desc, max_particles), offsetof(pic_layout, nspecies),
+         offsetof(pic_layout, prev_cell), offsetof(pic_layout, id), sizeof(pic_adjoint_buffers));
   return 0; }
 """
     with tempfile.TemporaryDirectory() as d:
@@ -58,7 +58,7 @@ int main(void){
     import ctypes as C
     got = [C.sizeof(pk.GridDesc), C.sizeof(pk.Sizes), C.sizeof(pk.Buffers), C.sizeof(pk.Layout),
            C.sizeof(pk.ParticleView), pk.GridDesc.max_particles.offset, pk.Layout.nspecies.offset,
-           pk.Layout.prev_cell.offset]
+           pk.Layout.prev_cell.offset, pk.Layout.id.offset, C.sizeof(pk.AdjointBuffers)]
     assert [int(x) for x in out] == got
 
 

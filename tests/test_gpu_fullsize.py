@@ -80,6 +80,7 @@ def _check_samples(wl, prec, perms, gpu, dt, steps, nsample, rng):
         n = q["cell"].shape[0]
         pick = np.sort(rng.choice(n, size=min(nsample, n), replace=False))
         orig = _original_index(perms, s, pick)
+        np.testing.assert_array_equal(q["id"][pick], orig)  # ids carried through every sort
         sub = _subset(wl.species[s], orig)
         ref, _ = O.run(g, dt, steps, EB, [sub], sort_every=0)
         r = ref[0]

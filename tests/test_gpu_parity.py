@@ -46,6 +46,7 @@ def test_one_step_parity(name, prec):
     for s, (r, q) in enumerate(zip(ref, gpu)):
         perm = r["perm"]
         np.testing.assert_array_equal(q["perm"], perm)          # sort: bit-exact
+        np.testing.assert_array_equal(q["id"], perm)            # ids follow the sort
         np.testing.assert_array_equal(q["alive"], r["alive"])
         u_old = wl.species[s]["u"][perm]
         err_u = U.momentum_error(r, q, u_old, ks[s][perm])
@@ -74,8 +75,11 @@ def test_cart2d_ten_steps(prec):
     """The 2D Cartesian workload (64^2, 65,536 particles) for its 10 steps."""
     wl = W.cart2d()
     ref, Jref, gpu, Jg, dt, ctx = U.run_both(wl, prec, 10, print_case=f"[parity] cart2d 10 steps {prec}")
-    for r, q in zip(ref, gpu):
+    for s, (r, q) in enumerate(zip(ref, gpu)):
         np.testing.assert_array_equal(q["perm"], r["perm"])
+        ids = q["id"]  # after several sorts: still a permutation carrying every weight along
+        np.testing.assert_array_equal(np.sort(ids), np.arange(ids.shape[0]))
+        np.testing.assert_array_equal(q["w"], wl.species[s]["w"][ids])
         du = np.max(np.linalg.norm(q["u"] - r["u"], axis=1) / np.maximum(np.linalg.norm(r["u"], axis=1), 1e-3))
         same = np.all(q["cell"] == r["cell"], axis=1)
         print(f"  u err {du:.3e} cell mismatches {(~same).sum()}", flush=True)
