@@ -95,14 +95,18 @@ __device__ __forceinline__ int div_small(int x, int d, float inv) {
   return q;
 }
 
-// Calls f(x, comp, ix, iy, iz) for every element x = comp*T + ix + s0*iy +
-// s0*s1*iz (T = s0 s1 s2) of an ncomp-component tile, spread over the block.
-// Each thread owns one point of the plane of the first pdims axes (the x
-// row in 2D, the (x, y) plane in 3D) and walks the last axis and the
-// components, so elements need no division; a plane wider than the block
-// falls back to an element loop with divisions.
-template <class F>
-__device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int s1, int s2, F f) {
+// Visits every element x = comp*T + ix + s0*iy + s0*s1*iz (T = s0 s1 s2) of
+// an ncomp-component tile, spread over the block, in two phases per batch of
+// NB elements of a thread: v = get(x, comp, ix, iy, iz) for the whole batch
+// first (so that NB global loads are in flight together instead of one
+// waiting after another), then put(x, comp, ix, iy, iz, v).  Each thread owns
+// one point of the plane of the first pdims axes (the x row in 2D, the (x, y)
+// plane in 3D) and walks the last axis and the components, so elements need
+// no division; a plane wider than the block falls back to an element loop
+// with divisions.
+template <int NB, class V, class Get, class Put>
+__device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int s1, int s2,
+                                              Get get, Put put) {
   const int T = s0 * s1 * s2;
   const int P = (pdims == 2) ? s0 * s1 : s0;
   const int L = (pdims == 2) ? s2 : s1;
@@ -113,14 +117,41 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
     const int pt = (int)threadIdx.x - grp * P;
     const int iy0 = div_small(pt, s0, 1.0f / (float)s0);
     const int ix = pt - iy0 * s0;
-    for (int comp = 0; comp < ncomp; ++comp)
-      for (int w = grp; w < L; w += G) {
-        const int x = comp * T + pt + P * w;
-        if (pdims == 2)
-          f(x, comp, ix, iy0, w);
-        else
-          f(x, comp, ix, w, 0);
+    // elements per component of this thread: w = grp, grp + G, ... < L
+    const int nw = (L > grp) ? div_small(L - grp + G - 1, G, 1.0f / (float)G) : 0;
+    const int n = ncomp * nw;
+    int comp = 0, w = grp;
+    for (int k = 0; k < n; k += NB) {
+      V v[NB];
+      int c1 = comp, w1 = w;  // the put phase replays the walk from here
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (k + j < n) {
+          const int x = comp * T + pt + P * w;
+          v[j] = (pdims == 2) ? get(x, comp, ix, iy0, w) : get(x, comp, ix, w, 0);
+          w += G;
+          if (w >= L) {
+            w = grp;
+            ++comp;
+          }
+        }
       }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (k + j < n) {
+          const int x = c1 * T + pt + P * w1;
+          if (pdims == 2)
+            put(x, c1, ix, iy0, w1, v[j]);
+          else
+            put(x, c1, ix, w1, 0, v[j]);
+          w1 += G;
+          if (w1 >= L) {
+            w1 = grp;
+            ++c1;
+          }
+        }
+      }
+    }
   } else {
     const float iT = 1.0f / (float)T, i0f = 1.0f / (float)s0, i01 = 1.0f / (float)(s0 * s1);
     for (int x = threadIdx.x; x < ncomp * T; x += BLOCK) {
@@ -129,7 +160,8 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
       const int iz = div_small(rem, s0 * s1, i01);
       rem -= iz * s0 * s1;
       const int iy = div_small(rem, s0, i0f);
-      f(x, comp, rem - iy * s0, iy, iz);
+      const int ixx = rem - iy * s0;
+      put(x, comp, ixx, iy, iz, get(x, comp, ixx, iy, iz));
     }
   }
 }

@@ -422,9 +422,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   __syncthreads();
   // flush: one global atomic per nonzero tile value, periodic images resolved
   const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-  tile_for_each(6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
-                [&](int x, int comp, int ix, int iy, int iz) {
-                  const Acc acc = tile[x];
+  tile_for_each<8, Acc>(6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+                [&](int x, int, int, int, int) { return tile[x]; },
+                [&](int, int comp, int ix, int iy, int iz, Acc acc) {
                   if (acc == (Acc)0) return;
                   const Real v = (Real)ldexp((double)acc, -esc);
                   int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};

@@ -5,8 +5,8 @@
 // loaded with 16-byte vector accesses, or through the permutation of a sort
 // on the step that follows it).  Particles are kept in brick order by the
 // per-cell sort, so the chunk's cells form a compact box.  One LDS buffer
-// serves in turn as the block's copy of the fields over that box (FP32, when
-// it fits) for the push pass, and as the block's current tile over the box
+// serves in turn as the block's copy of the fields over that box (when it
+// fits) for the push pass, and as the block's current tile over the box
 // (plus the stencil halo) for the deposit pass: exact 64-bit fixed-point
 // accumulation in FP32 builds, double in FP64 builds, flushed with one global
 // atomic per nonzero value.  When the box outgrows the tile (particles
@@ -22,7 +22,13 @@ namespace picstep {
 constexpr int PPT = 4;                  // particles per thread
 constexpr int CHUNK = PUSH_CHUNK;       // particles per block
 static_assert(BLOCK * PPT == CHUNK, "chunk layout");
-constexpr int TILE_BYTES = 32768;       // LDS current tile per block
+// LDS buffer per block (field copy, then current tile).  The FP64 instances
+// run 2 blocks per CU (their registers allow no more), so they take a larger
+// buffer at no cost in occupancy.
+template <class Real>
+constexpr int tile_bytes() {
+  return sizeof(Real) == 8 ? 61440 : 32768;
+}
 
 // ---------------------------------------------------------------- vector I/O
 __device__ __forceinline__ void ld4(const float *p, float v[4]) {
@@ -339,8 +345,8 @@ template <int GEOM, int DIM, class Real>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(push_waves<GEOM, DIM, Real>(), 8)))
 void k_push(StepArgs<Real> A) {
   using Acc = typename TileAcc<Real>::type;
-  constexpr int TILE_VALS = TILE_BYTES / (int)sizeof(Acc);
-  constexpr int FIELD_VALS = TILE_BYTES / (int)sizeof(Real);
+  constexpr int TILE_VALS = tile_bytes<Real>() / (int)sizeof(Acc);
+  constexpr int FIELD_VALS = tile_bytes<Real>() / (int)sizeof(Real);
   // one LDS buffer: the block's copy of the fields during the push pass,
   // then its current tile during the deposit pass
   __shared__ union {
@@ -466,8 +472,8 @@ void k_push(StepArgs<Real> A) {
     TF *= fs[d];
   }
   const bool fit_j = 3 * T <= TILE_VALS;
-  // the field copy is made only when the whole box fits, in FP32 builds
-  const bool use_ft = sizeof(Real) == 4 && 6 * TF <= FIELD_VALS;
+  // the field copy is made only when the whole box fits
+  const bool use_ft = 6 * TF <= FIELD_VALS;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     t0[d] = lo[d] - 1;
@@ -513,20 +519,21 @@ void k_push(StepArgs<Real> A) {
   }
   if (use_ft) {
     const int npts = (int)g.npts;
-    tile_for_each(6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2],
-                  [&](int x, int comp, int ix, int iy, int iz) {
-                    int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
-                    bool ok = true;
+    tile_for_each<16, Real>(
+        6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2],
+        [&](int, int comp, int ix, int iy, int iz) {
+          int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
+          bool ok = true;
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d) {
-                      if (GEOM == 0)
-                        gi[d] = wrap_periodic(gi[d], g.n[d]);
-                      else
-                        ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
-                    }
-                    ftile[x] = ok ? A.EB[comp * npts + pad_index(g, gi[0], gi[1], gi[2], DIM)]
-                                  : (Real)0;
-                  });
+          for (int d = 0; d < DIM; ++d) {
+            if (GEOM == 0)
+              gi[d] = wrap_periodic(gi[d], g.n[d]);
+            else
+              ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
+          }
+          return ok ? A.EB[comp * npts + pad_index(g, gi[0], gi[1], gi[2], DIM)] : (Real)0;
+        },
+        [&](int x, int, int, int, int, Real v) { ftile[x] = v; });
     __syncthreads();
   }
 
@@ -638,9 +645,9 @@ void k_push(StepArgs<Real> A) {
   if (use_tile) {
     __syncthreads();
     const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-    tile_for_each(3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
-                  [&](int x, int comp, int ix, int iy, int iz) {
-                    const Acc acc = tile[x];
+    tile_for_each<8, Acc>(3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+                  [&](int x, int, int, int, int) { return tile[x]; },
+                  [&](int, int comp, int ix, int iy, int iz, Acc acc) {
                     if (acc == (Acc)0) return;
                     const Real v = (Real)ldexp((double)acc, -esc);
                     int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
