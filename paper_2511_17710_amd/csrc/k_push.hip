@@ -22,12 +22,12 @@ namespace picstep {
 constexpr int PPT = 4;                  // particles per thread
 constexpr int CHUNK = PUSH_CHUNK;       // particles per block
 static_assert(BLOCK * PPT == CHUNK, "chunk layout");
-// LDS buffer per block (field copy, then current tile).  The FP64 instances
-// run 2 blocks per CU (their registers allow no more), so they take a larger
-// buffer at no cost in occupancy.
+// LDS buffer per block (field copy, then current tile), sized so that the
+// blocks a CU holds at once share its 160 KB: the FP32 instances run 4 blocks
+// per CU, the FP64 ones 2 (their registers allow no more).
 template <class Real>
 constexpr int tile_bytes() {
-  return sizeof(Real) == 8 ? 61440 : 32768;
+  return sizeof(Real) == 8 ? 79872 : 39936;
 }
 
 // ---------------------------------------------------------------- vector I/O
@@ -122,24 +122,29 @@ __device__ __forceinline__ void unpack_m(int p, int m[3]) {
   m[2] = ((p >> 4) & 3) - 1;
 }
 
-// fields at the particle: from the block's LDS copy (FT: it covers every
-// live particle's stencil), else from global memory
-template <int DIM, class Real, bool FT>
+// fields at the particle: from the block's LDS copy when it covers the
+// particle's stencil (always, unless CHK: the copy is a cube smaller than the
+// chunk's box), else from global memory
+template <int DIM, class Real, bool CHK>
 __device__ __forceinline__ void particle_fields(const StepArgs<Real> &A, const FieldTile<Real> &ft,
                                                 const int i[3], const int shift[3],
                                                 const Stencil1<Real> st[3], Real F[6]) {
-  if (FT) {
-    int dsh[3] = {0, 0, 0};
+  int dsh[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < DIM; ++a)
-      if (shift[a] && i[a] < (A.g.n[a] >> 1)) dsh[a] = A.g.n[a];
-    interp6_tile<DIM, Real>(ft, dsh, st, F);
-  } else {
-    interp6<DIM, Real>(A.EB, A.g, st, F);
+  for (int a = 0; a < DIM; ++a)
+    if (shift[a] && i[a] < (A.g.n[a] >> 1)) dsh[a] = A.g.n[a];
+  bool in = true;
+  if (CHK) {
+    int ib[3] = {i[0] + dsh[0], i[1] + dsh[1], i[2] + dsh[2]};
+    in = fields_in_tile<DIM, Real>(ft, ib);
   }
+  if (in)
+    interp6_tile<DIM, Real>(ft, dsh, st, F);
+  else
+    interp6<DIM, Real>(A.EB, A.g, st, F);
 }
 
-template <int DIM, class Real, bool FT>
+template <int DIM, class Real, bool CHK>
 __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
                                              const int shift[3], int s, int32_t c,
                                              OffT<Real> q[3], Real u[3], int &mp, Real &dx3,
@@ -152,7 +157,7 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const Fiel
 #pragma unroll
   for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], (Real)PS::weight(q[a]));
   Real F[6];
-  particle_fields<DIM, Real, FT>(A, ft, i, shift, st, F);
+  particle_fields<DIM, Real, CHK>(A, ft, i, shift, st, F);
   Real E[3], B[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -231,7 +236,7 @@ __device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
   return pr;
 }
 
-template <int GEOM, class Real, bool FT>
+template <int GEOM, class Real, bool CHK>
 __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
                                             int s, int32_t c, OffT<Real> q[3], Real u[3],
                                             Real &phi, int &mp, Real &dx3, float &span) {
@@ -245,7 +250,7 @@ __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, const Field
   st[1] = stencil1(i[1], d2);
   Real F[6];
   const int noshift[3] = {0, 0, 0};
-  particle_fields<2, Real, FT>(A, ft, i, noshift, st, F);
+  particle_fields<2, Real, CHK>(A, ft, i, noshift, st, F);
   const Real k = (Real)A.sp.k[s];
   double dx1, dx2;
   Real phinew;
@@ -472,14 +477,13 @@ void k_push(StepArgs<Real> A) {
     TF *= fs[d];
   }
   const bool fit_j = 3 * T <= TILE_VALS;
-  // the field copy is made only when the whole box fits
-  const bool use_ft = 6 * TF <= FIELD_VALS;
+  const bool fit_f = 6 * TF <= FIELD_VALS;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     t0[d] = lo[d] - 1;
     f0[d] = lo[d] - 1;
   }
-  if (!fit_j) {  // uniform
+  if (!fit_j || !fit_f) {  // uniform
     __syncthreads();
     int sum[3] = {0, 0, 0}, nl[3] = {0, 0, 0};
 #pragma unroll
@@ -493,20 +497,30 @@ void k_push(StepArgs<Real> A) {
     block_sum3(sum, red);
     __syncthreads();
     block_sum3(nl, red);
-    constexpr int SIDE = tile_side(TILE_VALS / 3, DIM);  // 3 SIDE^DIM <= TILE_VALS
-    T = 1;
+    constexpr int SIDE = tile_side(TILE_VALS / 3, DIM);    // 3 SIDE^DIM <= TILE_VALS
+    constexpr int SIDEF = tile_side(FIELD_VALS / 6, DIM);  // 6 SIDEF^DIM <= FIELD_VALS
+    if (!fit_j) T = 1;
+    if (!fit_f) TF = 1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const int ctr = (sum[d] + nl[0] / 2) / nl[0];
-      ts[d] = SIDE;
-      t0[d] = ctr - SIDE / 2 - 1;
-      T *= ts[d];
+      if (!fit_j) {
+        ts[d] = SIDE;
+        t0[d] = ctr - SIDE / 2 - 1;
+        T *= ts[d];
+      }
+      if (!fit_f) {
+        fs[d] = SIDEF;
+        f0[d] = ctr - SIDEF / 2;
+        TF *= fs[d];
+      }
     }
   }
 
-  // copy the fields of the box (plus the stencil halo) into LDS (periodic
-  // images on Cartesian grids; on curvilinear grids points outside the
-  // padded lattice, which no particle stencil reaches, are left zero)
+  // copy the fields of the box (plus the stencil halo), or of the cube, into
+  // LDS (periodic images on Cartesian grids; on curvilinear grids points
+  // outside the padded lattice, which no particle stencil reaches, are left
+  // zero)
   FieldTile<Real> ft;
   ft.F = ftile;
   ft.T = (int)TF;
@@ -517,7 +531,7 @@ void k_push(StepArgs<Real> A) {
     ft.o[d] = f0[d];
     ft.ts[d] = fs[d];
   }
-  if (use_ft) {
+  {
     const int npts = (int)g.npts;
     tile_for_each<16, Real>(
         6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2],
@@ -542,16 +556,16 @@ void k_push(StepArgs<Real> A) {
   if (A.stats && A.deposit && threadIdx.x == 0) atomicAdd(A.stats, 1);
 
   // pass 1: interpolate, rotate, push and move every particle of the thread
-  // (steps 3-7), keeping the old position for the deposit; two instances,
-  // with the fields from LDS or from global memory
+  // (steps 3-7), keeping the old position for the deposit; two instances:
+  // every stencil inside the field copy, or tested one by one against it
   int32_t co[PPT];
   OffT<Real> qo[3][PPT];
   int mp[PPT];
   Real d3[PPT];
   float bmax = 0.0f;
   const Real qdt = (Real)A.sp.qdt[s];
-  auto push_pass = [&](auto from_lds) {
-    constexpr bool FT = decltype(from_lds)::value;
+  auto push_pass = [&](auto check) {
+    constexpr bool CHK = decltype(check)::value;
 #pragma unroll
     for (int r = 0; r < PPT; ++r) {
       co[r] = cl[r];
@@ -566,10 +580,10 @@ void k_push(StepArgs<Real> A) {
       float span = 0.0f;
       Real dx3;
       if (GEOM == 0) {
-        cl[r] = cart_push<DIM, Real, FT>(A, ft, shift, s, cl[r], q, u, mp[r], dx3, span);
+        cl[r] = cart_push<DIM, Real, CHK>(A, ft, shift, s, cl[r], q, u, mp[r], dx3, span);
       } else {
         Real p = ph[r];
-        cl[r] = axi_push<GEOM, Real, FT>(A, ft, s, cl[r], q, u, p, mp[r], dx3, span);
+        cl[r] = axi_push<GEOM, Real, CHK>(A, ft, s, cl[r], q, u, p, mp[r], dx3, span);
         ph[r] = p;
       }
       d3[r] = dx3;
@@ -580,10 +594,10 @@ void k_push(StepArgs<Real> A) {
       bmax = fmaxf(bmax, fabsf((float)(qdt * ww[r])) * fmaxf(span, fabsf((float)dx3)));
     }
   };
-  if (use_ft)
-    push_pass(std::true_type{});
-  else
+  if (fit_f)  // uniform
     push_pass(std::false_type{});
+  else
+    push_pass(std::true_type{});
 
   store_n(A.p.cell + p0, cnt, cl);
 #pragma unroll

@@ -15,7 +15,7 @@ Workloads (all seeded by numpy SeedSequence(17710 + index)):
                  theta=0.1, Bz=1 plus U[-0.1,0.1] E at each Yee point, 10 steps
   cart3d_128     3D Cartesian 128^3 periodic, 16 ppc per species, Maxwell-Juttner
                  theta=1 boosted to beta=0.3 along x, B0=1 z plus 32 random plane
-                 waves of amplitude 0.05, 100 steps, sort every 20
+                 waves of amplitude 0.05, 100 steps, sort every 5
   qsph_1024x512  2D quasi-spherical (r0=0, vartheta=0: log r), r in [1,20], cold
                  pair plasma 10 ppc, n ~ r^-2, dipole + corotation E (Omega=0.1)
   sph_1024x512   same on the uniform-r spherical metric
@@ -288,12 +288,12 @@ def cart2d(n=64, ppc=8, theta=0.1, steps=10, seed=None, index=1, shuffle=False):
 
 
 def cart3d(n=128, ppc=16, theta=1.0, drift=0.3, steps=100, nwaves=32, amp=0.05, seed=None,
-           index=2, name=None, shuffle=False, sort_every=4):
-    """3D periodic pair plasma.  The sort cadence of 4 steps keeps every
-    1024-particle chunk of a brick within the LDS current tile of the push
-    kernel: at CFL 0.45 and theta = 1 the chunk's bounding box grows by about
-    one cell per step, and past a side of 11 cells its particles spill to
-    global atomics."""
+           index=2, name=None, shuffle=False, sort_every=5):
+    """3D periodic pair plasma.  The sort cadence of 5 steps keeps every
+    1024-particle chunk of a brick within the LDS tiles of the push kernel:
+    at CFL 0.45 and theta = 1 the chunk's bounding box grows by about one cell
+    per step, and once box plus stencil halo exceeds about 11.8^3 cells its
+    outlying particles read the fields and deposit in global memory."""
     rp, ru, rf, rw, rW = _streams(index, seed)
     wl = Workload(name=name or f"cart3d_{n}", geom="cart", dim=3, n=(n, n, n),
                   lo=(0.0, 0.0, 0.0), hi=(float(n),) * 3, steps=steps, sort_every=sort_every,
@@ -311,7 +311,7 @@ def cart3d(n=128, ppc=16, theta=1.0, drift=0.3, steps=100, nwaves=32, amp=0.05, 
 
 
 def cart3d_adjoint(n=64, ppc=8, K=64, ckpt=8, seed=None, index=5):
-    wl = cart3d(n=n, ppc=ppc, steps=K, seed=seed, index=index,
+    wl = cart3d(n=n, ppc=ppc, steps=K, seed=seed, index=index, sort_every=4,
                 name=("cart3d_64_adj" if n == 64 else f"cart3d_{n}_adj"))
     rW = _streams(index, seed)[4]
     W = np.zeros((3,) + wl.padded_shape())

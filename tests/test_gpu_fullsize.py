@@ -164,18 +164,18 @@ def _check_continuity(wl, prec, gpu, Jg, dt):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cart3d_128_full(prec):
-    """67,108,864 particles, 5 steps with the workload's cadence of 4: a sort
-    before the first and before the fifth step."""
+    """67,108,864 particles, 6 steps with the workload's cadence of 5: a sort
+    before the first and before the sixth step."""
     print(f"[fullsize] cart3d_128 {prec}", flush=True)
     wl = _workload("cart3d_128")
     if prec == "f32":
         W.round_to_f32(wl)
-    assert wl.sort_every == 4
-    perms, gpu, Jg, dt = _gpu(wl, prec, (1, 4))
+    assert wl.sort_every == 5
+    perms, gpu, Jg, dt = _gpu(wl, prec, (1, 5))
     rng = np.random.default_rng(11)
-    _check_samples(wl, prec, perms, gpu, dt, 5, 3000, rng)
-    _check_box(wl, prec, perms, gpu, Jg, dt, 5, (40, 70, 100), (10, 10, 10))
-    _check_box(wl, prec, perms, gpu, Jg, dt, 5, (0, 0, 120), (6, 6, 8))  # periodic seams
+    _check_samples(wl, prec, perms, gpu, dt, 6, 3000, rng)
+    _check_box(wl, prec, perms, gpu, Jg, dt, 6, (40, 70, 100), (10, 10, 10))
+    _check_box(wl, prec, perms, gpu, Jg, dt, 6, (0, 0, 120), (6, 6, 8))  # periodic seams
     _check_continuity(wl, prec, gpu, Jg, dt)
 
 
