@@ -96,17 +96,18 @@ __device__ __forceinline__ int div_small(int x, int d, float inv) {
 }
 
 // Visits every element x = comp*T + ix + s0*iy + s0*s1*iz (T = s0 s1 s2) of
-// an ncomp-component tile, spread over the block, in two phases per batch of
-// NB elements of a thread: v = get(x, comp, ix, iy, iz) for the whole batch
-// first (so that NB global loads are in flight together instead of one
-// waiting after another), then put(x, comp, ix, iy, iz, v).  Each thread owns
-// one point of the plane of the first pdims axes (the x row in 2D, the (x, y)
-// plane in 3D) and walks the last axis and the components, so elements need
-// no division; a plane wider than the block falls back to an element loop
-// with divisions.
-template <int NB, class V, class Get, class Put>
+// an ncomp-component tile, spread over the block.  Each thread owns one point
+// of the plane of the first pdims axes (the x row in 2D, the (x, y) plane in
+// 3D) and walks the last axis (w: y in 2D, z in 3D) and the components, so
+// elements need no division; per thread ps = plane(ix, iy) is formed once
+// (iy = 0 in 2D).  Elements go in batches of NB per thread: v = get(ps, x,
+// comp, w) for the whole batch first (so that NB global loads are in flight
+// together instead of one waiting after another), then put(ps, x, comp, w,
+// v).  A plane wider than the block falls back to an element loop with
+// divisions.
+template <int NB, class V, class Plane, class Get, class Put>
 __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int s1, int s2,
-                                              Get get, Put put) {
+                                              Plane plane, Get get, Put put) {
   const int T = s0 * s1 * s2;
   const int P = (pdims == 2) ? s0 * s1 : s0;
   const int L = (pdims == 2) ? s2 : s1;
@@ -117,6 +118,7 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
     const int pt = (int)threadIdx.x - grp * P;
     const int iy0 = div_small(pt, s0, 1.0f / (float)s0);
     const int ix = pt - iy0 * s0;
+    const auto ps = plane(ix, pdims == 2 ? iy0 : 0);
     // elements per component of this thread: w = grp, grp + G, ... < L
     const int nw = (L > grp) ? div_small(L - grp + G - 1, G, 1.0f / (float)G) : 0;
     const int n = ncomp * nw;
@@ -127,8 +129,7 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (k + j < n) {
-          const int x = comp * T + pt + P * w;
-          v[j] = (pdims == 2) ? get(x, comp, ix, iy0, w) : get(x, comp, ix, w, 0);
+          v[j] = get(ps, comp * T + pt + P * w, comp, w);
           w += G;
           if (w >= L) {
             w = grp;
@@ -139,11 +140,7 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (k + j < n) {
-          const int x = c1 * T + pt + P * w1;
-          if (pdims == 2)
-            put(x, c1, ix, iy0, w1, v[j]);
-          else
-            put(x, c1, ix, w1, 0, v[j]);
+          put(ps, c1 * T + pt + P * w1, c1, w1, v[j]);
           w1 += G;
           if (w1 >= L) {
             w1 = grp;
@@ -160,11 +157,88 @@ __device__ __forceinline__ void tile_for_each(int ncomp, int pdims, int s0, int 
       const int iz = div_small(rem, s0 * s1, i01);
       rem -= iz * s0 * s1;
       const int iy = div_small(rem, s0, i0f);
-      const int ixx = rem - iy * s0;
-      put(x, comp, ixx, iy, iz, get(x, comp, ixx, iy, iz));
+      const auto ps = plane(rem - iy * s0, pdims == 2 ? iy : 0);
+      const int w = (pdims == 2) ? iz : iy;
+      put(ps, x, comp, w, get(ps, x, comp, w));
     }
   }
 }
+
+// tile_for_each for a tile that maps affinely onto a global array: element
+// (comp, plane point, w) sits at g = plane(ix, iy) + comp*cstride + w*wstride
+// there.  x and g advance by additions only, so an element costs a few
+// instructions: v = get(g, x) for a batch of NB, then put(g, x, v).  Same
+// walk and the same element loop fallback as tile_for_each.
+template <int NB, class V, class Plane, class Get, class Put>
+__device__ __forceinline__ void tile_for_each_affine(int ncomp, int pdims, int s0, int s1, int s2,
+                                                     int cstride, int wstride, Plane plane,
+                                                     Get get, Put put) {
+  const int T = s0 * s1 * s2;
+  const int P = (pdims == 2) ? s0 * s1 : s0;
+  const int L = (pdims == 2) ? s2 : s1;
+  if (P <= BLOCK) {
+    const int G = BLOCK / P;
+    const int grp = div_small((int)threadIdx.x, P, 1.0f / (float)P);
+    if (grp >= G) return;
+    const int pt = (int)threadIdx.x - grp * P;
+    const int iy0 = div_small(pt, s0, 1.0f / (float)s0);
+    const int ix = pt - iy0 * s0;
+    const int nw = (L > grp) ? div_small(L - grp + G - 1, G, 1.0f / (float)G) : 0;
+    const int n = ncomp * nw;
+    // steps along the walk and from the last w of a component to the first
+    // of the next
+    const int dx = P * G, dg = wstride * G;
+    const int dxc = T - dx * (nw - 1), dgc = cstride - dg * (nw - 1);
+    // unsigned: the offset one step past the last element may exceed 2^31
+    unsigned x = pt + P * grp;
+    unsigned gi = plane(ix, pdims == 2 ? iy0 : 0) + wstride * grp;
+    int cw = 0;  // position along the walk within the component
+    for (int k = 0; k < n; k += NB) {
+      V v[NB];
+      unsigned x1 = x, g1 = gi;  // the put phase replays the walk from here
+      int c1 = cw;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (k + j < n) {
+          v[j] = get((int)gi, (int)x);
+          const bool last = ++cw == nw;
+          x += last ? dxc : dx;
+          gi += last ? dgc : dg;
+          cw = last ? 0 : cw;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (k + j < n) {
+          put((int)g1, (int)x1, v[j]);
+          const bool last = ++c1 == nw;
+          x1 += last ? dxc : dx;
+          g1 += last ? dgc : dg;
+          c1 = last ? 0 : c1;
+        }
+      }
+    }
+  } else {
+    const float iT = 1.0f / (float)T, i0f = 1.0f / (float)s0, i01 = 1.0f / (float)(s0 * s1);
+    for (int x = threadIdx.x; x < ncomp * T; x += BLOCK) {
+      const int comp = div_small(x, T, iT);
+      int rem = x - comp * T;
+      const int iz = div_small(rem, s0 * s1, i01);
+      rem -= iz * s0 * s1;
+      const int iy = div_small(rem, s0, i0f);
+      const int w = (pdims == 2) ? iz : iy;
+      const int gi = plane(rem - iy * s0, pdims == 2 ? iy : 0) + comp * cstride + w * wstride;
+      put(gi, x, get(gi, x));
+    }
+  }
+}
+
+// a thread's point of a tile plane: its padded-lattice offset and whether it
+// lies on the lattice
+struct PlanePt {
+  int off;
+  bool ok;
+};
 
 // block-wide sum of three ints (256 threads)
 __device__ __forceinline__ void block_sum3(int v[3], int *red) {

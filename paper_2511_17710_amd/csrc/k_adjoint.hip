@@ -422,18 +422,37 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   __syncthreads();
   // flush: one global atomic per nonzero tile value, periodic images resolved
   const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-  tile_for_each<8, Acc>(6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
-                [&](int x, int, int, int, int) { return tile[x]; },
-                [&](int, int comp, int ix, int iy, int iz, Acc acc) {
-                  if (acc == (Acc)0) return;
-                  const Real v = (Real)ldexp((double)acc, -esc);
-                  int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
+  constexpr int WA = DIM - 1;  // walked axis
+  const int wstride = (DIM == 3) ? np01 : np0;
+  bool inside = true;  // uniform: the tile lies inside the padded lattice
 #pragma unroll
-                  for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
-                  const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
-                                   ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
-                  atomic_add_r(A.dEB + gidx, v);
-                });
+  for (int d = 0; d < DIM; ++d) inside = inside && t0[d] >= -NG && t0[d] + ts[d] <= g.n[d] + NG;
+  if (inside) {  // ghost values are folded into the active cells afterwards
+    tile_for_each_affine<8, Acc>(
+        6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2], npts, wstride,
+        [&](int ix, int iy) {
+          return pad_index(g, t0[0] + ix, t0[1] + ((DIM == 3) ? iy : 0), t0[2], DIM);
+        },
+        [&](int, int x) { return tile[x]; },
+        [&](int gi, int, Acc acc) {
+          if (acc != (Acc)0) atomic_add_r(A.dEB + gi, (Real)ldexp((double)acc, -esc));
+        });
+    return;
+  }
+  tile_for_each<8, Acc>(
+      6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+      [&](int ix, int iy) {
+        const int gx = wrap_periodic(t0[0] + ix, g.n[0]);
+        const int gy = (DIM == 3) ? wrap_periodic(t0[1] + iy, g.n[1]) : 0;
+        return PlanePt{(gx + NG) + ((DIM == 3) ? np0 * (gy + NG) : 0), true};
+      },
+      [&](const PlanePt &, int x, int, int) { return tile[x]; },
+      [&](const PlanePt &pp, int, int comp, int w, Acc acc) {
+        if (acc == (Acc)0) return;
+        const Real v = (Real)ldexp((double)acc, -esc);
+        const int gw = wrap_periodic(t0[WA] + w, g.n[WA]);
+        atomic_add_r(A.dEB + comp * npts + pp.off + wstride * (gw + NG), v);
+      });
 }
 
 template <class Real>

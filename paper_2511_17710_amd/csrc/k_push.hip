@@ -533,21 +533,47 @@ void k_push(StepArgs<Real> A) {
   }
   {
     const int npts = (int)g.npts;
+    constexpr int WA = DIM - 1;  // walked axis (z in 3D, y in 2D)
+    const int wstride = (DIM == 3) ? g.np[0] * g.np[1] : g.np[0];
+    bool inside = true;  // uniform: the tile lies inside the padded lattice
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) inside = inside && f0[d] >= -NG && f0[d] + fs[d] <= g.n[d] + NG;
+    if (inside) {  // the ghost layers hold the periodic images (or the caller's values)
+      tile_for_each_affine<16, Real>(
+          6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2], npts, wstride,
+          [&](int ix, int iy) {
+            return pad_index(g, f0[0] + ix, f0[1] + ((DIM == 3) ? iy : 0), f0[2], DIM);
+          },
+          [&](int gi, int) { return A.EB[gi]; }, [&](int, int x, Real v) { ftile[x] = v; });
+    } else {
+    // a point's padded index is its plane part (x, and y in 3D) plus the
+    // walked axis times its stride; periodic images on Cartesian grids,
+    // points outside the padded lattice (curvilinear) read as zero
     tile_for_each<16, Real>(
         6, DIM == 3 ? 2 : 1, fs[0], fs[1], fs[2],
-        [&](int, int comp, int ix, int iy, int iz) {
-          int gi[3] = {f0[0] + ix, f0[1] + iy, f0[2] + iz};
+        [&](int ix, int iy) {
+          int gx = f0[0] + ix, gy = f0[1] + iy;
           bool ok = true;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            if (GEOM == 0)
-              gi[d] = wrap_periodic(gi[d], g.n[d]);
-            else
-              ok = ok && gi[d] >= -NG && gi[d] < g.n[d] + NG;
+          if (GEOM == 0) {
+            gx = wrap_periodic(gx, g.n[0]);
+            if (DIM == 3) gy = wrap_periodic(gy, g.n[1]);
+          } else {
+            ok = gx >= -NG && gx < g.n[0] + NG;
+            if (DIM == 3) ok = ok && gy >= -NG && gy < g.n[1] + NG;
           }
-          return ok ? A.EB[comp * npts + pad_index(g, gi[0], gi[1], gi[2], DIM)] : (Real)0;
+          return PlanePt{(gx + NG) + ((DIM == 3) ? g.np[0] * (gy + NG) : 0), ok};
         },
-        [&](int x, int, int, int, int, Real v) { ftile[x] = v; });
+        [&](const PlanePt &pp, int, int comp, int w) {
+          int gw = f0[WA] + w;
+          bool ok = pp.ok;
+          if (GEOM == 0)
+            gw = wrap_periodic(gw, g.n[WA]);
+          else
+            ok = ok && gw >= -NG && gw < g.n[WA] + NG;
+          return ok ? A.EB[comp * npts + pp.off + wstride * (gw + NG)] : (Real)0;
+        },
+        [&](const PlanePt &, int x, int, int, Real v) { ftile[x] = v; });
+    }
     __syncthreads();
   }
 
@@ -659,20 +685,42 @@ void k_push(StepArgs<Real> A) {
   if (use_tile) {
     __syncthreads();
     const int np0 = g.np[0], np01 = g.np[0] * g.np[1], npts = (int)g.npts;
-    tile_for_each<8, Acc>(3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
-                  [&](int x, int, int, int, int) { return tile[x]; },
-                  [&](int, int comp, int ix, int iy, int iz, Acc acc) {
-                    if (acc == (Acc)0) return;
-                    const Real v = (Real)ldexp((double)acc, -esc);
-                    int gi[3] = {t0[0] + ix, t0[1] + iy, t0[2] + iz};
-                    if (GEOM == 0) {  // periodic: add straight into the image
+    constexpr int WA = DIM - 1;  // walked axis
+    const int wstride = (DIM == 3) ? np01 : np0;
+    bool inside = true;  // uniform: the tile lies inside the padded lattice
 #pragma unroll
-                      for (int d = 0; d < DIM; ++d) gi[d] = wrap_periodic(gi[d], g.n[d]);
-                    }
-                    const int gidx = comp * npts + (gi[0] + NG) + np0 * (gi[1] + NG) +
-                                     ((DIM == 3) ? np01 * (gi[2] + NG) : 0);
-                    atomic_add_r(A.J + gidx, v);
-                  });
+    for (int d = 0; d < DIM; ++d) inside = inside && t0[d] >= -NG && t0[d] + ts[d] <= g.n[d] + NG;
+    if (inside) {  // ghost values are folded into the active cells after the step
+      tile_for_each_affine<8, Acc>(
+          3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2], npts, wstride,
+          [&](int ix, int iy) {
+            return pad_index(g, t0[0] + ix, t0[1] + ((DIM == 3) ? iy : 0), t0[2], DIM);
+          },
+          [&](int, int x) { return tile[x]; },
+          [&](int gi, int, Acc acc) {
+            if (acc != (Acc)0) atomic_add_r(A.J + gi, (Real)ldexp((double)acc, -esc));
+          });
+    } else {
+    // periodic grids add straight into the image of each tile point
+    tile_for_each<8, Acc>(
+        3, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
+        [&](int ix, int iy) {
+          int gx = t0[0] + ix, gy = t0[1] + iy;
+          if (GEOM == 0) {
+            gx = wrap_periodic(gx, g.n[0]);
+            if (DIM == 3) gy = wrap_periodic(gy, g.n[1]);
+          }
+          return PlanePt{(gx + NG) + ((DIM == 3) ? np0 * (gy + NG) : 0), true};
+        },
+        [&](const PlanePt &, int x, int, int) { return tile[x]; },
+        [&](const PlanePt &pp, int, int comp, int w, Acc acc) {
+          if (acc == (Acc)0) return;
+          const Real v = (Real)ldexp((double)acc, -esc);
+          int gw = t0[WA] + w;
+          if (GEOM == 0) gw = wrap_periodic(gw, g.n[WA]);
+          atomic_add_r(A.J + comp * npts + pp.off + wstride * (gw + NG), v);
+        });
+    }
   }
 }
 
