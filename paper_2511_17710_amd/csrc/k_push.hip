@@ -315,12 +315,14 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
     za[a] = PS::exact(qo[a]);
     zb[a] = PS::exact(qn[a]) + (double)m[a];
   }
-  ZigZag<Real> z;
+  // segment data in FP64 (exact differences of exact positions), rounded to
+  // Real only where a float contribution is formed
+  ZigZag<double> z;
   const int nseg = (m[0] | m[1] | m[2]) ? 2 : 1;
   if (nseg == 1)
-    straight<DIM, Real>(za, zb, z);
+    straight<DIM, double>(za, zb, z);
   else
-    zigzag<DIM, Real>(za, m, zb, z);
+    zigzag<DIM, double>(za, m, zb, z);
   int ib[3] = {i[0], i[1], i[2]};
   if (GEOM == 0) {
 #pragma unroll
@@ -329,7 +331,11 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
   }
   const Real C = (Real)A.sp.qdt[s] * w;
   if (in_tile<DIM>(tile, ts, ib)) {
-    deposit<DIM>(tile, tile_coef(C, esc), ib, m, z, dx3, nseg);
+    if constexpr (sizeof(Real) == 4)
+      deposit_fixed<DIM>(tile, ldexp((double)A.sp.qdt[s] * (double)w, esc), ib, m, z,
+                         (double)dx3, nseg);
+    else
+      deposit<DIM>(tile, C, ib, m, z, dx3, nseg);
   } else {
     deposit<DIM>(glob, C, i, m, z, dx3, nseg);
     if (A.stats) atomicAdd(A.stats + 1, 1);
@@ -643,7 +649,7 @@ void k_push(StepArgs<Real> A) {
   // |dx3|) to any tile value (its segment fluxes along a dimension sum to
   // its displacement there, span the largest; shape weights are at most 1;
   // the out-of-plane current of 2D grids carries dx3).  With B 2^esc < 2^49
-  // one contribution stays below the 2^51 of fixed_round and the CHUNK
+  // one contribution stays below the 2^51 of the rounding and the CHUNK
   // particles of the block below 2^60, and small displacements (cold plasma)
   // keep the full 48-bit resolution relative to the largest of the block.
   int esc = 0;

@@ -337,9 +337,9 @@ struct DepTarget {
 // the global array; periodic ghosts are folded after the step).
 // nseg = 1: a step that stays in its cell is one straight segment (the two
 // collinear halves of the zig-zag carry, summed, exactly its flux).
-template <int DIM, class Real, class Acc>
+template <int DIM, class Real, class Acc, class Z>
 __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const int i0[3],
-                                        const int m[3], const ZigZag<Real> &z, Real dx3,
+                                        const int m[3], const ZigZag<Z> &z, Real dx3,
                                         int nseg = 2) {
   const int cs = t.cs, sy = t.sy, sz = t.sz;
 #pragma unroll
@@ -349,8 +349,8 @@ __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const i
     const int Jc = i0[1] + (s ? m[1] : 0) - t.o[1];
     const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) - t.o[2] : 0;
     const int base = I + sy * Jc + sz * K;
-    const Real Fx = z.F[s][0], Fy = z.F[s][1];
-    const Real Wx = z.W[s][0], Wy = z.W[s][1];
+    const Real Fx = (Real)z.F[s][0], Fy = (Real)z.F[s][1];
+    const Real Wx = (Real)z.W[s][0], Wy = (Real)z.W[s][1];
     if (DIM == 2) {
       const Real cx = C * Fx, cy = C * Fy;
       atomic_add_r(t.J + base, cx * ((Real)1 - Wy));
@@ -365,7 +365,7 @@ __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const i
       atomic_add_r(J3 + sy, h * (((Real)1 - Wx) * Wy - cxy));
       atomic_add_r(J3 + sy + 1, h * (Wx * Wy + cxy));
     } else {
-      const Real Fz = z.F[s][2], Wz = z.W[s][2];
+      const Real Fz = (Real)z.F[s][2], Wz = (Real)z.W[s][2];
       const Real cx = C * Fx, cy = C * Fy, cz = C * Fz;
       const Real cyz = Fy * Fz * (Real)(1.0 / 12.0);
       const Real cxz = Fx * Fz * (Real)(1.0 / 12.0);
@@ -386,6 +386,68 @@ __device__ __forceinline__ void deposit(const DepTarget<Acc> &t, Real C, const i
       atomic_add_r(J3 + 1, cz * (Wx * gy - cxy));
       atomic_add_r(J3 + sy, cz * (gx * Wy - cxy));
       atomic_add_r(J3 + sy + 1, cz * (Wx * Wy + cxy));
+    }
+  }
+}
+
+// The same scatter into the fixed-point tile of FP32 builds, in FP64 from the
+// exact segment data: each contribution c*s is rounded to an integer by one
+// fused multiply-add onto 1.5*2^52 (|c*s| < 2^51), so it costs two FP64
+// operations and an integer add; C carries the tile's 2^esc scale.
+__device__ __forceinline__ void fixed_add(long long *p, double c, double s) {
+  const long long v = __double_as_longlong(fma(c, s, 0x1.8p52)) - 0x4338000000000000LL;
+  atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
+template <int DIM>
+__device__ __forceinline__ void deposit_fixed(const DepTarget<long long> &t, double C,
+                                              const int i0[3], const int m[3],
+                                              const ZigZag<double> &z, double dx3, int nseg) {
+  const int cs = t.cs, sy = t.sy, sz = t.sz;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (s >= nseg) break;
+    const int I = i0[0] + (s ? m[0] : 0) - t.o[0];
+    const int Jc = i0[1] + (s ? m[1] : 0) - t.o[1];
+    const int K = (DIM == 3) ? i0[2] + (s ? m[2] : 0) - t.o[2] : 0;
+    const int base = I + sy * Jc + sz * K;
+    const double Fx = z.F[s][0], Fy = z.F[s][1];
+    const double Wx = z.W[s][0], Wy = z.W[s][1];
+    const double gx = 1.0 - Wx, gy = 1.0 - Wy;
+    if (DIM == 2) {
+      const double cx = C * Fx, cy = C * Fy;
+      fixed_add(t.J + base, cx, gy);
+      fixed_add(t.J + base + sy, cx, Wy);
+      fixed_add(t.J + cs + base, cy, gx);
+      fixed_add(t.J + cs + base + 1, cy, Wx);
+      const double h = C * dx3 * (nseg == 1 ? 1.0 : 0.5);  // dx3 shared by the segments
+      const double cxy = Fx * Fy * (1.0 / 12.0);
+      long long *J3 = t.J + 2 * cs + base;
+      fixed_add(J3, h, fma(gx, gy, cxy));
+      fixed_add(J3 + 1, h, fma(Wx, gy, -cxy));
+      fixed_add(J3 + sy, h, fma(gx, Wy, -cxy));
+      fixed_add(J3 + sy + 1, h, fma(Wx, Wy, cxy));
+    } else {
+      const double Fz = z.F[s][2], Wz = z.W[s][2], gz = 1.0 - Wz;
+      const double cx = C * Fx, cy = C * Fy, cz = C * Fz;
+      const double cyz = Fy * Fz * (1.0 / 12.0);
+      const double cxz = Fx * Fz * (1.0 / 12.0);
+      const double cxy = Fx * Fy * (1.0 / 12.0);
+      long long *J1 = t.J + base;
+      fixed_add(J1, cx, fma(gy, gz, cyz));
+      fixed_add(J1 + sy, cx, fma(Wy, gz, -cyz));
+      fixed_add(J1 + sz, cx, fma(gy, Wz, -cyz));
+      fixed_add(J1 + sz + sy, cx, fma(Wy, Wz, cyz));
+      long long *J2 = t.J + cs + base;
+      fixed_add(J2, cy, fma(gx, gz, cxz));
+      fixed_add(J2 + 1, cy, fma(Wx, gz, -cxz));
+      fixed_add(J2 + sz, cy, fma(gx, Wz, -cxz));
+      fixed_add(J2 + sz + 1, cy, fma(Wx, Wz, cxz));
+      long long *J3 = t.J + 2 * cs + base;
+      fixed_add(J3, cz, fma(gx, gy, cxy));
+      fixed_add(J3 + 1, cz, fma(Wx, gy, -cxy));
+      fixed_add(J3 + sy, cz, fma(gx, Wy, -cxy));
+      fixed_add(J3 + sy + 1, cz, fma(Wx, Wy, cxy));
     }
   }
 }
