@@ -117,8 +117,8 @@ hipError_t launch_zero(Real *A, int64_t n, hipStream_t s);
 struct SortScratch {
   uint32_t *keys[2];
   int32_t *vals[2];
-  int32_t *hist;      // 256 * max_tiles
-  int32_t *bsum;      // block sums of the scan
+  int32_t *hist;      // tile histograms, tile-major: max_tiles x 256
+  int32_t *bsum;      // column sums of tile chunks: SCAN_CHUNKS x 256
   int64_t max_tiles;
 };
 hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
@@ -132,6 +132,6 @@ hipError_t launch_scatter_back(const Real *src, Real *dst, int64_t off, int64_t 
                                const int32_t *perm, hipStream_t s);
 
 constexpr int SORT_TILE = 4096;  // keys per block in the radix passes
-constexpr int SCAN_CHUNK = 4096; // elements per block of the scan
+constexpr int SCAN_CHUNKS = 64;  // most tile chunks of the histogram scan
 
 }  // namespace picstep

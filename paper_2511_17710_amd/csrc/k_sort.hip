@@ -3,9 +3,10 @@
 // Least-significant-digit radix sort on a cell key that orders cells brick by
 // brick (8-bit digits; dead particles carry the largest key; the first pass
 // forms the keys from the cells), so equal keys keep their previous order and
-// the permutation is unique.  Per pass: tile histograms (digit-major matrix),
-// one exclusive scan of that matrix, and a stable in-tile ranking with wave
-// ballots followed by a scatter.  A gather then reorders every SoA array into
+// the permutation is unique.  Per pass: tile histograms (one row of 256
+// counts per tile), an exclusive scan of the matrix in digit-major order (the
+// start of every digit of every tile), and a stable in-tile ranking with
+// wave ballots followed by a scatter.  A gather then reorders every SoA array into
 // the second particle set.
 #include "internal.h"
 
@@ -83,61 +84,52 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(KeySource src, int6
     if (i < n) atomicAdd(&h[(src.key(i) >> shift) & (RADIX - 1)], 1);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  hist[(int64_t)blockIdx.x * RADIX + threadIdx.x] = h[threadIdx.x];  // one 1 KB row
 }
 
-// exclusive scan of a long int array: chunk scans, scan of chunk sums, add
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_chunks(int32_t *__restrict__ a, int64_t L,
-                                                              int32_t *__restrict__ bsum) {
-  __shared__ int sw[SORT_THREADS / 64];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SORT_ITEMS;
-  int v[SORT_ITEMS];
+// Exclusive scan of the tile-major histogram matrix H[tile][digit] in
+// digit-major order: H[t][d] becomes the number of keys with a smaller digit
+// plus those with digit d in earlier tiles.  Thread = digit throughout, so
+// every access is a coalesced row.  (1) column sums of chunks of ct tiles,
+// (2) one block scans those sums down the chunks and across the digits,
+// (3) each chunk rescans its rows from its chunk start.
+__global__ __launch_bounds__(RADIX) void k_col_sums(const int32_t *__restrict__ H, int64_t ntiles,
+                                                    int64_t ct, int32_t *__restrict__ S) {
+  const int64_t t0 = (int64_t)blockIdx.x * ct, t1 = min(t0 + ct, ntiles);
   int sum = 0;
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int64_t i = base + j;
-    v[j] = (i < L) ? a[i] : 0;
-    sum += v[j];
-  }
-  int tot;
-  int pre = block_exclusive_scan(sum, &tot, sw);
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int64_t i = base + j;
-    if (i < L) a[i] = pre;
-    pre += v[j];
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+#pragma unroll 16
+  for (int64_t t = t0; t < t1; ++t) sum += H[t * RADIX + threadIdx.x];
+  S[(int64_t)blockIdx.x * RADIX + threadIdx.x] = sum;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_sums(int32_t *__restrict__ bsum, int nb) {
-  __shared__ int sw[SORT_THREADS / 64];
-  int v[SORT_ITEMS];
-  int sum = 0;
+__global__ __launch_bounds__(RADIX) void k_col_scan(int32_t *__restrict__ S, int nchunks) {
+  __shared__ int sw[RADIX / 64];
+  int v[SCAN_CHUNKS];  // the whole column in registers: loads issued together
 #pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int i = threadIdx.x * SORT_ITEMS + j;
-    v[j] = (i < nb) ? bsum[i] : 0;
-    sum += v[j];
-  }
-  int tot;
-  int pre = block_exclusive_scan(sum, &tot, sw);
+  for (int c = 0; c < SCAN_CHUNKS; ++c) v[c] = (c < nchunks) ? S[c * RADIX + threadIdx.x] : 0;
+  int run = 0;
 #pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int i = threadIdx.x * SORT_ITEMS + j;
-    if (i < nb) bsum[i] = pre;
-    pre += v[j];
+  for (int c = 0; c < SCAN_CHUNKS; ++c) {
+    const int x = v[c];
+    v[c] = run;
+    run += x;
   }
+  int all;
+  const int base = block_exclusive_scan(run, &all, sw);  // keys with a smaller digit
+#pragma unroll
+  for (int c = 0; c < SCAN_CHUNKS; ++c)
+    if (c < nchunks) S[c * RADIX + threadIdx.x] = v[c] + base;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_scan_add(int32_t *__restrict__ a, int64_t L,
-                                                           const int32_t *__restrict__ bsum) {
-  const int32_t add = bsum[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int64_t i = base + (int64_t)j * SORT_THREADS + threadIdx.x;
-    if (i < L) a[i] += add;
+__global__ __launch_bounds__(RADIX) void k_col_apply(int32_t *__restrict__ H, int64_t ntiles,
+                                                     int64_t ct, const int32_t *__restrict__ S) {
+  const int64_t t0 = (int64_t)blockIdx.x * ct, t1 = min(t0 + ct, ntiles);
+  int run = S[(int64_t)blockIdx.x * RADIX + threadIdx.x];
+#pragma unroll 16
+  for (int64_t t = t0; t < t1; ++t) {
+    const int v = H[t * RADIX + threadIdx.x];
+    H[t * RADIX + threadIdx.x] = run;
+    run += v;
   }
 }
 
@@ -166,7 +158,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
   const int nvalid = (int)min((int64_t)SORT_TILE, n - t0);
 #pragma unroll
   for (int ww = 0; ww < NW; ++ww) cnt[ww][threadIdx.x] = 0;
-  const int goff = hist[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  const int goff = hist[(int64_t)blockIdx.x * RADIX + threadIdx.x];
   __syncthreads();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint32_t k[ROUNDS];
@@ -246,9 +238,8 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
   if (n <= 0) return hipSuccess;
   const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   if (ntiles > S.max_tiles) return hipErrorInvalidValue;
-  const int64_t L = (int64_t)RADIX * ntiles;
-  const int64_t nchunks = (L + SCAN_CHUNK - 1) / SCAN_CHUNK;
-  if (nchunks > SCAN_CHUNK) return hipErrorInvalidValue;
+  const int64_t ct = (ntiles + SCAN_CHUNKS - 1) / SCAN_CHUNKS;  // tiles per chunk
+  const int64_t nchunks = (ntiles + ct - 1) / ct;                // <= SCAN_CHUNKS
   const uint32_t deadkey = 1u << (keybits - 1);
   const int passes = (keybits + 7) / 8;
   for (int ps = 0; ps < passes; ++ps) {
@@ -257,11 +248,11 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
     KeySource ks{S.keys[src], S.vals[src], ps == 0 ? cell : nullptr, g, deadkey};
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks, n,
                        shift, S.hist, ntiles);
-    hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist,
-                       L, S.bsum);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SORT_THREADS), 0, s, S.bsum, (int)nchunks);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nchunks), dim3(SORT_THREADS), 0, s, S.hist, L,
+    hipLaunchKernelGGL(k_col_sums, dim3((unsigned)nchunks), dim3(RADIX), 0, s, S.hist, ntiles, ct,
                        S.bsum);
+    hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(RADIX), 0, s, S.bsum, (int)nchunks);
+    hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(RADIX), 0, s, S.hist, ntiles,
+                       ct, S.bsum);
     int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks,
                        (ps == passes - 1) ? nullptr : S.keys[dst], vdst, n, shift, S.hist,

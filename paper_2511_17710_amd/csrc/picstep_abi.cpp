@@ -686,7 +686,7 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   c->s_hist = o;
   o += align_up((uint64_t)256 * c->max_tiles * 4, ALIGN);
   c->s_bsum = o;
-  o += align_up((uint64_t)SCAN_CHUNK * 4, ALIGN);
+  o += align_up((uint64_t)SCAN_CHUNKS * 256 * 4, ALIGN);
   c->s_perm = o;
   o += ai;
   c->s_stats = o;
