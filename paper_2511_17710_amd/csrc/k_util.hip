@@ -6,43 +6,55 @@ namespace picstep {
 
 constexpr int UT = 256;
 
-__device__ __forceinline__ void unpad(const GridConst &g, int64_t q, int ii[3]) {
-  ii[0] = (int)(q % g.np[0]) - NG;
-  const int64_t r = q / g.np[0];
-  ii[1] = (int)(r % g.np[1]) - NG;
-  ii[2] = (g.dim == 3) ? (int)(r / g.np[1]) - NG : 0;
+// Ghost slab of dimension dd: its 2*NG ghost layers times the padded extent
+// of the other dimensions.  Thread q of ncomp * slab_points(g, dd) maps to
+// component c and unpadded coordinates ii (ii[dd] in [-NG, 0) or [n, n + NG)).
+__device__ __forceinline__ int slab_points(const GridConst &g, int dd) {
+  int e = 2 * NG;
+  for (int d = 0; d < g.dim; ++d)
+    if (d != dd) e *= g.np[d];
+  return e;
+}
+__device__ __forceinline__ void slab_point(const GridConst &g, int dd, int r, int ii[3]) {
+  int ext[3] = {g.np[0], g.np[1], (g.dim == 3) ? g.np[2] : 1};
+  ext[dd] = 2 * NG;
+  ii[0] = r % ext[0] - NG;
+  r /= ext[0];
+  ii[1] = r % ext[1] - NG;
+  ii[2] = (g.dim == 3) ? r / ext[1] - NG : 0;
+  if (ii[dd] >= 0) ii[dd] += g.n[dd];  // the high layers
 }
 
 // copy the periodic image into every ghost point of dimension dd
 template <class Real>
 __global__ __launch_bounds__(UT) void k_fill_ghosts(GridConst g, Real *A, int ncomp, int dd) {
-  const int64_t q = (int64_t)blockIdx.x * UT + threadIdx.x;
-  if (q >= g.npts * ncomp) return;
-  const int64_t c = q / g.npts, pt = q % g.npts;
+  const int per = slab_points(g, dd);
+  const int q = blockIdx.x * UT + threadIdx.x;
+  if (q >= per * ncomp) return;
+  const int c = q / per;
   int ii[3];
-  unpad(g, pt, ii);
-  const int v = ii[dd];
-  if (v >= 0 && v < g.n[dd]) return;
-  int s = v % g.n[dd];
+  slab_point(g, dd, q - c * per, ii);
+  const int64_t at = c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim);
+  int s = ii[dd] % g.n[dd];
   if (s < 0) s += g.n[dd];
   ii[dd] = s;
-  A[q] = A[c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim)];
+  A[at] = A[c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim)];
 }
 
 // add every ghost point of dimension dd into its periodic image, zero the ghost
 template <class Real>
 __global__ __launch_bounds__(UT) void k_fold_ghosts(GridConst g, Real *A, int ncomp, int dd) {
-  const int64_t q = (int64_t)blockIdx.x * UT + threadIdx.x;
-  if (q >= g.npts * ncomp) return;
-  const int64_t c = q / g.npts, pt = q % g.npts;
+  const int per = slab_points(g, dd);
+  const int q = blockIdx.x * UT + threadIdx.x;
+  if (q >= per * ncomp) return;
+  const int c = q / per;
   int ii[3];
-  unpad(g, pt, ii);
-  const int v = ii[dd];
-  if (v >= 0 && v < g.n[dd]) return;
-  const Real x = A[q];
-  A[q] = (Real)0;
+  slab_point(g, dd, q - c * per, ii);
+  const int64_t at = c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim);
+  const Real x = A[at];
+  A[at] = (Real)0;
   if (x == (Real)0) return;
-  int s = v % g.n[dd];
+  int s = ii[dd] % g.n[dd];
   if (s < 0) s += g.n[dd];
   ii[dd] = s;
   atomic_add_r(A + c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim), x);
@@ -54,23 +66,29 @@ __global__ __launch_bounds__(UT) void k_zero(Real *A, int64_t n) {
   if (q < n) A[q] = (Real)0;
 }
 
+// blocks for the ghost slab of dimension dd (host side of slab_points)
+unsigned slab_blocks(const GridConst &g, int dd, int ncomp) {
+  int64_t e = 2 * NG;
+  for (int d = 0; d < g.dim; ++d)
+    if (d != dd) e *= g.np[d];
+  return (unsigned)((e * ncomp + UT - 1) / UT);
+}
+
 template <class Real>
 hipError_t launch_fill_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s) {
   if (g.geom != 0) return hipSuccess;
-  const int64_t tot = g.npts * ncomp;
-  const unsigned nb = (unsigned)((tot + UT - 1) / UT);
   for (int dd = 0; dd < g.dim; ++dd)
-    hipLaunchKernelGGL((k_fill_ghosts<Real>), dim3(nb), dim3(UT), 0, s, g, A, ncomp, dd);
+    hipLaunchKernelGGL((k_fill_ghosts<Real>), dim3(slab_blocks(g, dd, ncomp)), dim3(UT), 0, s, g,
+                       A, ncomp, dd);
   return hipGetLastError();
 }
 
 template <class Real>
 hipError_t launch_fold_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s) {
   if (g.geom != 0) return hipSuccess;
-  const int64_t tot = g.npts * ncomp;
-  const unsigned nb = (unsigned)((tot + UT - 1) / UT);
   for (int dd = g.dim - 1; dd >= 0; --dd)
-    hipLaunchKernelGGL((k_fold_ghosts<Real>), dim3(nb), dim3(UT), 0, s, g, A, ncomp, dd);
+    hipLaunchKernelGGL((k_fold_ghosts<Real>), dim3(slab_blocks(g, dd, ncomp)), dim3(UT), 0, s, g,
+                       A, ncomp, dd);
   return hipGetLastError();
 }
 
