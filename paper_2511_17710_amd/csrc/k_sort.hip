@@ -138,20 +138,17 @@ __global__ __launch_bounds__(RADIX) void k_col_apply(int32_t *__restrict__ H, in
 // holding the same digit, a lane's rank is the count of those peers below it
 // plus the wave's running count of the digit (a wave-private LDS counter
 // advanced by the lowest peer).  Rounds run in key order and waves are
-// ordered by their per-digit prefix, so equal digits keep their order.  The
-// tile is then staged in digit order in LDS and written out with consecutive
-// threads on consecutive destinations.
+// ordered by their per-digit prefix, so equal digits keep their order.  Each
+// key then goes straight from registers to the tile's start of its digit in
+// the global order plus its rank: lanes of a round holding the same digit
+// write consecutive addresses, and sorted input gives long such runs.
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     KeySource src, uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n, int shift,
     const int32_t *__restrict__ hist, int64_t ntiles) {
   constexpr int NW = SORT_THREADS / 64;
   constexpr int PER_WAVE = SORT_TILE / NW;
   constexpr int ROUNDS = PER_WAVE / 64;
-  __shared__ uint32_t sk[SORT_TILE];
-  __shared__ int32_t sv[SORT_TILE];
   __shared__ int cnt[NW][RADIX];
-  __shared__ int dstart[RADIX];
-  __shared__ int sw[NW];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int64_t t0 = (int64_t)blockIdx.x * SORT_TILE;
@@ -170,6 +167,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const bool ok = e < nvalid;
     k[j] = ok ? src.key(t0 + e) : 0u;
     v[j] = ok ? src.val(t0 + e) : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < ROUNDS; ++j) {
+    const int e = w * PER_WAVE + j * 64 + lane;
+    const bool ok = e < nvalid;
     const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
     uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -185,23 +187,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     if (ok && r == 0) cnt[w][dg] = base + __popcll(peers);
   }
   __syncthreads();
-  // per digit (one per thread): tile start and the waves' prefixes
+  // per digit (one per thread): global start of each wave's keys of the digit
   {
     const int d = threadIdx.x;
-    int c[NW], tot = 0;
+    int run = goff;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) {
-      c[ww] = cnt[ww][d];
-      tot += c[ww];
-    }
-    int all;
-    const int st = block_exclusive_scan(tot, &all, sw);
-    dstart[d] = st;
-    int run = st;
-#pragma unroll
-    for (int ww = 0; ww < NW; ++ww) {
+      const int c = cnt[ww][d];
       cnt[ww][d] = run;
-      run += c[ww];
+      run += c;
     }
   }
   __syncthreads();
@@ -210,24 +204,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const int e = w * PER_WAVE + j * 64 + lane;
     if (e < nvalid) {
       const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
-      const int lp = cnt[w][dg] + rk[j];
-      sk[lp] = k[j];
-      sv[lp] = v[j];
-    }
-  }
-  __syncthreads();
-  // digit start of the tile in the global order, per digit
-  cnt[0][threadIdx.x] = goff;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < SORT_ITEMS; ++j) {
-    const int e = j * SORT_THREADS + threadIdx.x;
-    if (e < nvalid) {
-      const uint32_t key = sk[e];
-      const uint32_t dg = (key >> shift) & (RADIX - 1);
-      const int64_t dst = (int64_t)cnt[0][dg] + (e - dstart[dg]);
-      if (kout) kout[dst] = key;  // the last pass keeps only the permutation
-      vout[dst] = sv[e];
+      const int64_t dst = (int64_t)cnt[w][dg] + rk[j];
+      if (kout) kout[dst] = k[j];  // the last pass keeps only the permutation
+      vout[dst] = v[j];
     }
   }
 }
