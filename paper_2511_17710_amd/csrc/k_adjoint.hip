@@ -10,19 +10,55 @@
 
 namespace picstep {
 
-constexpr int ADJ_TILE_BYTES = 32768;  // LDS tile of dL/d(fields) per block
+// LDS buffer per block: the copy of the fields and of dL/dJ over the block's
+// box, then the tile of dL/d(fields).  Sized like the forward kernel's: the
+// FP32 instances run 4 blocks per CU, the FP64 ones 2.
+template <class Real>
+constexpr int adj_tile_bytes() {
+  return sizeof(Real) == 8 ? 79872 : 39936;
+}
 
-// forward interpolation of one component that also returns the corner values
+// the 2^DIM lattice values around A[base] (row stride sy, plane stride sz)
 template <int DIM, class Real>
-__device__ __forceinline__ void corners(const Real *__restrict__ A, const GridConst &g, int bx,
-                                        int by, int bz, Real c[8], int idx[8]) {
-  const int np0 = g.np[0], np01 = np0 * g.np[1];
-  const int base = pad_index(g, bx, by, bz, DIM);
+__device__ __forceinline__ void corners(const Real *__restrict__ A, int base, int sy, int sz,
+                                        Real c[8]) {
 #pragma unroll
-  for (int e = 0; e < (1 << DIM); ++e) {
-    const int o = (e & 1) + ((e >> 1) & 1) * np0 + ((DIM == 3) ? ((e >> 2) & 1) * np01 : 0);
-    idx[e] = base + o;
-    c[e] = A[base + o];
+  for (int e = 0; e < (1 << DIM); ++e)
+    c[e] = A[base + (e & 1) + ((e >> 1) & 1) * sy + ((DIM == 3) ? ((e >> 2) & 1) * sz : 0)];
+}
+
+// copy ncomp components of a padded global array over the box [o, o + s) of
+// (unwrapped) cells into LDS, component-major, x fastest; Cartesian grids
+// take the periodic image of points outside the padded lattice
+template <int DIM, class Real>
+__device__ __forceinline__ void stage_box(const GridConst &g, const Real *__restrict__ src,
+                                          int ncomp, const int o[3], const int sz3[3],
+                                          Real *dst) {
+  const int npts = (int)g.npts;
+  const int wstride = (DIM == 3) ? g.np[0] * g.np[1] : g.np[0];
+  bool inside = true;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) inside = inside && o[d] >= -NG && o[d] + sz3[d] <= g.n[d] + NG;
+  if (inside) {
+    tile_for_each_affine<16, Real>(
+        ncomp, DIM == 3 ? 2 : 1, sz3[0], sz3[1], sz3[2], npts, wstride,
+        [&](int ix, int iy) {
+          return pad_index(g, o[0] + ix, o[1] + ((DIM == 3) ? iy : 0), o[2], DIM);
+        },
+        [&](int gi, int) { return src[gi]; }, [&](int, int x, Real v) { dst[x] = v; });
+  } else {
+    constexpr int WA = DIM - 1;
+    tile_for_each<16, Real>(
+        ncomp, DIM == 3 ? 2 : 1, sz3[0], sz3[1], sz3[2],
+        [&](int ix, int iy) {
+          const int gx = wrap_periodic(o[0] + ix, g.n[0]);
+          const int gy = (DIM == 3) ? wrap_periodic(o[1] + iy, g.n[1]) : 0;
+          return PlanePt{(gx + NG) + ((DIM == 3) ? g.np[0] * (gy + NG) : 0), true};
+        },
+        [&](const PlanePt &pp, int, int comp, int w) {
+          return src[comp * npts + pp.off + wstride * (wrap_periodic(o[WA] + w, g.n[WA]) + NG)];
+        },
+        [&](const PlanePt &, int x, int, int, Real v) { dst[x] = v; });
   }
 }
 
@@ -36,8 +72,13 @@ template <int DIM, class Real>
 __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   using PS = Pos<Real>;
   using Acc = typename TileAcc<Real>::type;
-  constexpr int TILE_VALS = ADJ_TILE_BYTES / (int)sizeof(Acc);
-  __shared__ Acc tile[TILE_VALS];
+  constexpr int TILE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Acc);
+  constexpr int STAGE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Real);
+  __shared__ union {
+    Acc j[TILE_VALS];
+    Real f[STAGE_VALS];
+  } lds;
+  Acc *tile = lds.j;
   __shared__ int red[6 * (BLOCK / 64)];
   const GridConst &g = A.g;
   const int64_t blk = xcd_chunk(blockIdx.x, A.sp.blk0[MAXSP]);  // blk0[MAXSP] = all blocks
@@ -79,13 +120,19 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     }
     block_minmax3(lo, hi, red);
   }
-  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1};
-  int T = 1;
+  int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1}, j0[3] = {0, 0, 0}, js[3] = {1, 1, 1};
+  int T = 1, TJ = 1;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    ts[d] = hi[d] - lo[d] + 3;
+    ts[d] = hi[d] - lo[d] + 3;  // interpolation stencils: cells i-1 .. i+1
+    js[d] = hi[d] - lo[d] + 4;  // deposit stencils: cells i-1 .. i+2
+    j0[d] = lo[d] - 1;
     T *= ts[d];
+    TJ *= js[d];
   }
+  // the box's fields (6 T values) and dL/dJ (3 TJ) fit in the buffer: copy
+  // them (uniform), and every live particle reads them from LDS
+  const bool stage = 6 * T <= TILE_VALS && 6 * T + (A.lamJ ? 3 * TJ : 0) <= STAGE_VALS;
   if (6 * T <= TILE_VALS) {
 #pragma unroll
     for (int d = 0; d < DIM; ++d) t0[d] = lo[d] - 1;
@@ -107,7 +154,12 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
       T *= ts[d];
     }
   }
-  for (int x = threadIdx.x; x < 6 * T; x += BLOCK) tile[x] = (Acc)0;
+  if (stage) {
+    stage_box<DIM, Real>(g, A.EB, 6, t0, ts, lds.f);
+    if (A.lamJ) stage_box<DIM, Real>(g, A.lamJ, 3, j0, js, lds.f + 6 * T);
+    __syncthreads();
+  }
+  const int dsh[3] = {ib[0] - i[0], ib[1] - i[1], ib[2] - i[2]};  // unwrapped - stored
 
   Real Fbar[6] = {0, 0, 0, 0, 0, 0};
   Stencil1<Real> st[3];
@@ -129,7 +181,20 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
 #pragma unroll
   for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], d[a]);
   Real F[6];
-  interp6<DIM, Real>(A.EB, g, st, F);
+  FieldTile<Real> ft;
+  ft.F = lds.f;
+  ft.T = T;
+  ft.sy = ts[0];
+  ft.sz = ts[0] * ts[1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ft.o[a] = t0[a];
+    ft.ts[a] = ts[a];
+  }
+  if (stage)
+    interp6_tile<DIM, Real>(ft, dsh, st, F);
+  else
+    interp6<DIM, Real>(A.EB, g, st, F);
   Real E[3], B[3], sc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -197,13 +262,18 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     }
     const Real dx3 = (DIM == 2) ? dtr * un[2] * ig : (Real)0;
     Real Fb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Wb[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    const int cs = (int)g.npts, sy = g.np[0], sz = g.np[0] * g.np[1];
+    // dL/dJ from the LDS copy (box frame) or from global memory
+    const Real *L = stage ? lds.f + 6 * T : A.lamJ;
+    const int cs = stage ? TJ : (int)g.npts;
+    const int sy = stage ? js[0] : g.np[0];
+    const int sz = stage ? js[0] * js[1] : g.np[0] * g.np[1];
 #pragma unroll
     for (int sg = 0; sg < 2; ++sg) {
       const int I = i[0] + (sg ? m[0] : 0), Jc = i[1] + (sg ? m[1] : 0);
       const int K = (DIM == 3) ? i[2] + (sg ? m[2] : 0) : 0;
-      const int base = pad_index(g, I, Jc, K, DIM);
-      const Real *L = A.lamJ;
+      const int base = stage ? (I + dsh[0] - j0[0]) + sy * (Jc + dsh[1] - j0[1]) +
+                                   ((DIM == 3) ? sz * (K + dsh[2] - j0[2]) : 0)
+                             : pad_index(g, I, Jc, K, DIM);
       const Real Fx = Fs[sg][0], Fy = Fs[sg][1], Wx = Ws[sg][0], Wy = Ws[sg][1];
       if (DIM == 2) {
         const Real l10 = L[base], l11 = L[base + sy];
@@ -335,8 +405,13 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     const Real fy = sy2 ? st[1].fh : st[1].f0;
     const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
     Real cv[8];
-    int ix[8];
-    corners<DIM, Real>(A.EB + c * (int)g.npts, g, bx, by, bz, cv, ix);
+    if (stage)
+      corners<DIM, Real>(lds.f + c * T, (bx + dsh[0] - t0[0]) + ft.sy * (by + dsh[1] - t0[1]) +
+                                            ((DIM == 3) ? ft.sz * (bz + dsh[2] - t0[2]) : 0),
+                         ft.sy, ft.sz, cv);
+    else
+      corners<DIM, Real>(A.EB + c * (int)g.npts, pad_index(g, bx, by, bz, DIM), g.np[0],
+                         g.np[0] * g.np[1], cv);
     const Real gx = (Real)1 - fx, gy = (Real)1 - fy, gz = (Real)1 - fz;
     const Real fb = Fbar[c];
     bmax = fmaxf(bmax, fabsf((float)fb));
@@ -362,6 +437,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
   // Fixed-point scale 2^esc (FP32): one particle adds at most max|dL/dF| to a
   // tile value (interpolation weights are at most 1), so with B 2^esc < 2^49
   // the BLOCK particles of the block stay below 2^57.
+  // the copies are done with: the buffer becomes the tile
+  __syncthreads();
+  for (int x = threadIdx.x; x < 6 * T; x += BLOCK) tile[x] = (Acc)0;
   int esc = 0;
   if (sizeof(Acc) == 8 && sizeof(Real) == 4) {
     const float B = block_max_nonneg(bmax, red);  // also orders the tile zeroing
@@ -373,7 +451,6 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
     bool in = true;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) in = in && (ib[d] - 1 >= t0[d]) && (ib[d] + 1 < t0[d] + ts[d]);
-    const int dsh[3] = {ib[0] - i[0], ib[1] - i[1], ib[2] - i[2]};
     const int sy = ts[0], sz = ts[0] * ts[1];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
