@@ -68,8 +68,17 @@ __device__ __forceinline__ void stage_box(const GridConst &g, const Real *__rest
 // fixed point in FP32 builds, scaled by the block's largest |dL/dF|) and
 // flushed with one global atomic per nonzero value; particles whose stencil
 // leaves the tile scatter with global atomics.
+// Waves per SIMD the register allocation must allow: the FP32 instances run
+// faster at 4 (a few spills) than uncapped at 3 (0.457 -> 0.41 ms per step on
+// the 64^3 workload); the FP64 ones stay uncapped.
+template <class Real>
+constexpr int adj_waves() {
+  return sizeof(Real) == 4 ? 4 : 1;
+}
+
 template <int DIM, class Real>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_cart(AdjArgs<Real> A) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(adj_waves<Real>(), 8)))
+void k_adjoint_cart(AdjArgs<Real> A) {
   using PS = Pos<Real>;
   using Acc = typename TileAcc<Real>::type;
   constexpr int TILE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Acc);
