@@ -138,10 +138,14 @@ __global__ __launch_bounds__(RADIX) void k_col_apply(int32_t *__restrict__ H, in
 // holding the same digit, a lane's rank is the count of those peers below it
 // plus the wave's running count of the digit (a wave-private LDS counter
 // advanced by the lowest peer).  Rounds run in key order and waves are
-// ordered by their per-digit prefix, so equal digits keep their order.  Each
-// key then goes straight from registers to the tile's start of its digit in
-// the global order plus its rank: lanes of a round holding the same digit
-// write consecutive addresses, and sorted input gives long such runs.
+// ordered by their per-digit prefix, so equal digits keep their order.  Then
+// either (STAGE) the tile is staged in digit order in LDS and written with
+// consecutive threads on consecutive destinations -- the first pass, whose
+// low digit is spread over many short runs after the particles have drifted
+// -- or each key goes straight from registers to its slot: lanes of a round
+// holding the same digit write consecutive addresses, and the higher digits
+// of nearly sorted keys come in long runs.
+template <bool STAGE>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     KeySource src, uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n, int shift,
     const int32_t *__restrict__ hist, int64_t ntiles) {
@@ -187,26 +191,74 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     if (ok && r == 0) cnt[w][dg] = base + __popcll(peers);
   }
   __syncthreads();
-  // per digit (one per thread): global start of each wave's keys of the digit
-  {
-    const int d = threadIdx.x;
-    int run = goff;
+  if constexpr (STAGE) {
+    __shared__ uint32_t sk[SORT_TILE];
+    __shared__ int32_t sv[SORT_TILE];
+    __shared__ int dstart[RADIX];
+    __shared__ int sw[NW];
+    {  // per digit (one per thread): tile start and the waves' prefixes
+      const int d = threadIdx.x;
+      int c[NW], tot = 0;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) {
-      const int c = cnt[ww][d];
-      cnt[ww][d] = run;
-      run += c;
+      for (int ww = 0; ww < NW; ++ww) {
+        c[ww] = cnt[ww][d];
+        tot += c[ww];
+      }
+      int all;
+      const int st = block_exclusive_scan(tot, &all, sw);
+      dstart[d] = st;
+      int run = st;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) {
+        cnt[ww][d] = run;
+        run += c[ww];
+      }
     }
-  }
-  __syncthreads();
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < ROUNDS; ++j) {
-    const int e = w * PER_WAVE + j * 64 + lane;
-    if (e < nvalid) {
-      const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
-      const int64_t dst = (int64_t)cnt[w][dg] + rk[j];
-      if (kout) kout[dst] = k[j];  // the last pass keeps only the permutation
-      vout[dst] = v[j];
+    for (int j = 0; j < ROUNDS; ++j) {
+      const int e = w * PER_WAVE + j * 64 + lane;
+      if (e < nvalid) {
+        const int lp = cnt[w][(k[j] >> shift) & (RADIX - 1)] + rk[j];
+        sk[lp] = k[j];
+        sv[lp] = v[j];
+      }
+    }
+    __syncthreads();
+    cnt[0][threadIdx.x] = goff;  // the digit's start of the tile in the global order
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SORT_ITEMS; ++j) {
+      const int e = j * SORT_THREADS + threadIdx.x;
+      if (e < nvalid) {
+        const uint32_t key = sk[e];
+        const uint32_t dg = (key >> shift) & (RADIX - 1);
+        const int64_t dst = (int64_t)cnt[0][dg] + (e - dstart[dg]);
+        if (kout) kout[dst] = key;  // the last pass keeps only the permutation
+        vout[dst] = sv[e];
+      }
+    }
+  } else {
+    {  // per digit (one per thread): global start of each wave's keys of the digit
+      const int d = threadIdx.x;
+      int run = goff;
+#pragma unroll
+      for (int ww = 0; ww < NW; ++ww) {
+        const int c = cnt[ww][d];
+        cnt[ww][d] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ROUNDS; ++j) {
+      const int e = w * PER_WAVE + j * 64 + lane;
+      if (e < nvalid) {
+        const uint32_t dg = (k[j] >> shift) & (RADIX - 1);
+        const int64_t dst = (int64_t)cnt[w][dg] + rk[j];
+        if (kout) kout[dst] = k[j];  // the last pass keeps only the permutation
+        vout[dst] = v[j];
+      }
     }
   }
 }
@@ -233,9 +285,13 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
     hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(RADIX), 0, s, S.hist, ntiles,
                        ct, S.bsum);
     int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s, ks,
-                       (ps == passes - 1) ? nullptr : S.keys[dst], vdst, n, shift, S.hist,
-                       ntiles);
+    uint32_t *kdst = (ps == passes - 1) ? nullptr : S.keys[dst];
+    if (ps == 0)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
+                         ks, kdst, vdst, n, shift, S.hist, ntiles);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
+                         ks, kdst, vdst, n, shift, S.hist, ntiles);
   }
   return hipGetLastError();
 }
