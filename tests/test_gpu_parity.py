@@ -149,6 +149,47 @@ def test_sort_reorder_fused_into_the_step(prec):
     assert U.rel_l2(ja, jb) < (1e-13 if prec == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_unsorted_3d_tile_fallbacks(prec):
+    """No sort at all on a shuffled 24^3 box: every 1024-particle chunk spans
+    the whole grid, so each block copies only a centred cube of the fields
+    and keeps a centred cube of the current, and most particles read the
+    fields from and deposit into global memory (the per-particle fallbacks
+    of the push kernel), one step from the loaded state."""
+    wl = W.cart3d(n=24, ppc=4, steps=1, seed=39, shuffle=True)
+    tol = U.TOL[prec]
+    ref, Jref, gpu, Jg, dt, ctx = U.run_both(wl, prec, 1, sort_every=0,
+                                             print_case=f"[parity] unsorted 3d {prec} 1 step")
+    g, EB = U.oracle_fields(wl, prec)
+    ks = U.kick_scale(wl, g, EB, dt)
+    for s, (r, q) in enumerate(zip(ref, gpu)):
+        np.testing.assert_array_equal(q["alive"], r["alive"])
+        err_u = U.momentum_error(r, q, wl.species[s]["u"], ks[s])
+        same = np.all(q["cell"] == r["cell"], axis=1)
+        if prec == "f64":
+            assert same.all(), f"{(~same).sum()} cell mismatches"
+        else:
+            bad = ~same & ~U.near_face(r["offs"][:, :wl.dim], 1e-5)
+            assert not bad.any(), f"{bad.sum()} cell mismatches away from faces"
+        assert err_u <= tol["u"], (prec, err_u)
+        doff = np.abs(q["offs"] - r["offs"])[same]
+        assert doff.max(initial=0) <= tol["offs"], doff.max()
+    eJ = U.rel_l2(Jg, Jref)
+    cres = U.continuity_of(wl, Jg, gpu, dt)
+    print(f"  J relL2={eJ:.3e} continuity={cres:.3e}", flush=True)
+    assert eJ <= tol["J"], eJ
+    assert cres <= tol["cont"], cres
+    # the fallbacks were taken: one more step, counted
+    import torch
+    ctx.timing_enable(True)
+    ctx.push_deposit(dt, 1)
+    torch.cuda.synchronize()
+    t = ctx.timing_read()
+    print(f"  blocks {t['push_blocks']} particles depositing globally {t['push_global_particles']}",
+          flush=True)
+    assert t["push_global_particles"] > t["push_blocks"]
+
+
 def test_edge_cases_empty_ragged_single_cell():
     """A species with no particles, a ragged particle count, and every particle
     of a species in one cell (one huge sort bucket)."""
