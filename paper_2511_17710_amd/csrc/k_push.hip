@@ -83,8 +83,16 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 }
 
 // ---------------------------------------------------------------- block -> chunk
-__device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0) {
-  const int64_t b = xcd_chunk(blockIdx.x, sp.blk0[MAXSP]);  // blk0[MAXSP] = all blocks
+// XCD-aware order (each XCD's L2 keeps the fields and current around its
+// neighbouring chunks), except on the step that reads through a sort's
+// permutation (plain): there the blocks in flight on all XCDs sweep about
+// one plane of bricks at a time, so the particles that came from the plane
+// before are read while it is still cached; under the XCD order they were
+// last touched many L2 capacities earlier (push 3.4 -> 3.2 ms on that step).
+__device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0,
+                                             bool plain) {
+  // blk0[MAXSP] = all blocks
+  const int64_t b = plain ? (int64_t)blockIdx.x : xcd_chunk(blockIdx.x, sp.blk0[MAXSP]);
   s = 0;
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
@@ -370,7 +378,7 @@ void k_push(StepArgs<Real> A) {
   const GridConst &g = A.g;
   int s;
   int64_t c0;
-  if (!locate_chunk(A.sp, s, c0)) return;  // uniform over the block
+  if (!locate_chunk(A.sp, s, c0, A.perm != nullptr)) return;  // uniform over the block
   const int64_t first = c0 + (int64_t)threadIdx.x * PPT;
   const int cnt = (int)max((int64_t)0, min((int64_t)PPT, A.sp.n[s] - first));
   const int64_t p0 = A.sp.off[s] + first;
