@@ -351,10 +351,10 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
 }
 
 // ---------------------------------------------------------------- the kernel
-// Waves per SIMD the register allocation must allow: the 32 KB LDS buffer
+// Waves per SIMD the register allocation must allow: the FP32 LDS buffer
 // already limits a CU to 4 blocks of 4 waves, and the Cartesian FP32 kernel
-// runs faster capped at that occupancy (128 VGPRs, a few spills) than
-// uncapped at 3 waves; the other instances would spill heavily.
+// runs faster capped at that occupancy (128 VGPRs) than uncapped at 3 waves;
+// the other instances would spill heavily.
 template <int GEOM, int DIM, class Real>
 constexpr int push_waves() {
   return (GEOM == 0 && sizeof(Real) == 4) ? 4 : 1;
