@@ -41,22 +41,34 @@ __global__ __launch_bounds__(UT) void k_fill_ghosts(GridConst g, Real *A, int nc
   A[at] = A[c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim)];
 }
 
-// add every ghost point of dimension dd into its periodic image, zero the ghost
+// add every ghost point into its periodic image (wrapped in every
+// dimension at once), zero the ghost.  One launch: thread q walks the ghost
+// slabs of the dimensions in turn and takes each point in the slab of its
+// lowest ghost dimension only, so every ghost point is visited once; the
+// images are active points, which no thread reads.
 template <class Real>
-__global__ __launch_bounds__(UT) void k_fold_ghosts(GridConst g, Real *A, int ncomp, int dd) {
-  const int per = slab_points(g, dd);
-  const int q = blockIdx.x * UT + threadIdx.x;
-  if (q >= per * ncomp) return;
+__global__ __launch_bounds__(UT) void k_fold_ghosts(GridConst g, Real *A, int ncomp) {
+  int q = blockIdx.x * UT + threadIdx.x;
+  int dd = 0, per = slab_points(g, 0);
+  while (q >= per * ncomp) {  // at most DIM iterations
+    q -= per * ncomp;
+    if (++dd >= g.dim) return;
+    per = slab_points(g, dd);
+  }
   const int c = q / per;
   int ii[3];
   slab_point(g, dd, q - c * per, ii);
+  for (int d = 0; d < dd; ++d)
+    if (ii[d] < 0 || ii[d] >= g.n[d]) return;  // taken in the slab of dimension d
   const int64_t at = c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim);
   const Real x = A[at];
   A[at] = (Real)0;
   if (x == (Real)0) return;
-  int s = ii[dd] % g.n[dd];
-  if (s < 0) s += g.n[dd];
-  ii[dd] = s;
+  for (int d = 0; d < g.dim; ++d) {
+    int s = ii[d] % g.n[d];
+    if (s < 0) s += g.n[d];
+    ii[d] = s;
+  }
   atomic_add_r(A + c * g.npts + (int64_t)pad_index(g, ii[0], ii[1], ii[2], g.dim), x);
 }
 
@@ -86,9 +98,10 @@ hipError_t launch_fill_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_
 template <class Real>
 hipError_t launch_fold_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s) {
   if (g.geom != 0) return hipSuccess;
-  for (int dd = g.dim - 1; dd >= 0; --dd)
-    hipLaunchKernelGGL((k_fold_ghosts<Real>), dim3(slab_blocks(g, dd, ncomp)), dim3(UT), 0, s, g,
-                       A, ncomp, dd);
+  int64_t threads = 0;  // all ghost slabs, one after the other
+  for (int dd = 0; dd < g.dim; ++dd) threads += (int64_t)slab_blocks(g, dd, ncomp) * UT;
+  hipLaunchKernelGGL((k_fold_ghosts<Real>), dim3((unsigned)((threads + UT - 1) / UT)), dim3(UT), 0,
+                     s, g, A, ncomp);
   return hipGetLastError();
 }
 
