@@ -275,7 +275,9 @@ pic_status pic_adjoint_workspace(const pic_ctx *ctx, int32_t K, int32_t m, uint6
 pic_status pic_forward_checkpointed(pic_ctx *ctx, double dt, int32_t K, int32_t m,
                                     void *workspace);
 
-/* Reverse sweep after pic_forward_checkpointed(dt, K, m, workspace).
+/* Reverse sweep after pic_forward_checkpointed(dt, K, m, workspace), with the
+ * same dt, K and m (PIC_E_STATE otherwise).  A context holds one checkpointed
+ * forward at a time: a second pic_forward_checkpointed replaces the first.
  * lamJ: device [3][npts] real (dL/dJ_K; may be NULL = 0); lam_u: device
  * [3][capacity] real in the particle order at step K (may be NULL).
  * Outputs (device, overwritten): dEB [6][npts] real, dL/d(fields) with

@@ -12,6 +12,9 @@ differentiated.  The K steps run exactly as ctx.push_deposit would run them,
 sorts of the context's cadence included: u_K is in the particle order at
 step K (ctx.checkpointed_order() gives each slot's step-0 slot), u0 and
 dL/du0 in the order at step 0.
+
+A context holds one checkpointed forward at a time: backward() of an
+earlier apply() on the same context, after a later one, raises.
 """
 import torch
 
@@ -24,18 +27,22 @@ class PushDeposit(torch.autograd.Function):
         arr = ctx.particle_arrays()
         for a in range(3):
             arr["u"][a].copy_(u0[a])
-        ctx.forward_checkpointed(dt, K, m)
+        gen = ctx.forward_checkpointed(dt, K, m)
         J = ctx.current().clone()
         arr = ctx.particle_arrays()
         uK = torch.stack([arr["u"][a] for a in range(3)]).clone()
         fctx.pic = ctx
         fctx.args = (dt, K, m)
+        fctx.generation = gen
         return J, uK
 
     @staticmethod
     def backward(fctx, gJ, gu):
         ctx = fctx.pic
         dt, K, m = fctx.args
+        if ctx.forward_generation != fctx.generation:
+            raise RuntimeError("PushDeposit.backward: a later forward on the same context replaced "
+                               "this one's checkpoints (one forward may be outstanding per context)")
         dEB, du0 = ctx.backward(dt, K, m, lamJ=gJ, lam_u=gu)
         return dEB, du0, None, None, None, None
 

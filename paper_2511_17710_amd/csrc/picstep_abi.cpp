@@ -56,6 +56,7 @@ struct pic_ctx {
   int64_t step = 0;
   double dx_min = 0;  // Sec. 2.4 CFL length
   int32_t ckpt_K = -1, ckpt_m = -1;  // last pic_forward_checkpointed
+  double ckpt_dt = 0.0;
   int64_t ckpt_step0 = 0;
   std::vector<int32_t> ckpt_sorts;  // steps n of that run that began with a sort
   bool perm_pending = false;        // a sort's reorder left to the next step
@@ -363,6 +364,7 @@ pic_status fwd_ckpt(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws) {
   const AdjLayout L = adj_layout(c, K, m);
   c->ckpt_K = -1;
   c->ckpt_m = m;
+  c->ckpt_dt = dt;
   c->ckpt_step0 = c->step;
   c->ckpt_sorts.clear();
   int32_t *perm = reinterpret_cast<int32_t *>(c->scratch + c->s_perm);
@@ -1135,6 +1137,8 @@ pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, c
   if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (c->ckpt_K != K || c->ckpt_m != m)
     return fail(c, PIC_E_STATE, "backward(K=%d, m=%d) without a matching forward_checkpointed", K, m);
+  if (dt != c->ckpt_dt)
+    return fail(c, PIC_E_STATE, "backward dt %.17g differs from the forward's %.17g", dt, c->ckpt_dt);
   const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;
   return c->eb == 8 ? bwd<double>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0)

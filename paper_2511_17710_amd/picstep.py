@@ -278,6 +278,8 @@ class Context:
             self._ws = ws
         self._check(lib().pic_forward_checkpointed(self.h, float(dt), int(K), int(m),
                                                    C.c_void_p(ws.data_ptr())), "forward_checkpointed")
+        self.forward_generation = getattr(self, "forward_generation", 0) + 1
+        return self.forward_generation
 
     def backward(self, dt, K, m, lamJ=None, lam_u=None):
         """dL/d(fields) [6, np3, np2, np1] and dL/du0 [3, capacity] for

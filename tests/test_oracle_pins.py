@@ -343,7 +343,7 @@ def test_offset_relative_move_equals_literal(geom, vt, rmax):
 
 def test_radial_exit_kills_after_depositing():
     """A particle leaving r_min or r_max deposits the whole step (ghost cells),
-    then is dead and never pushed again (reading of Sec. 4.2 ABSORB/ATMOSPHERE)."""
+    then is dead and never pushed again (reading of the ABSORB and ATMOSPHERE particle boundaries, Sec. 5.1.2 and Sec. 5.2)."""
     g = O.make_grid("sph", 2, (16, 16), (1.0, 0), (3.0, PI))
     EB = np.zeros((6,) + O.padded_shape(g))
     dt = O.dt_from_cfl(g, 0.45)
