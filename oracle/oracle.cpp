@@ -636,16 +636,91 @@ int64_t jidx(const Grid &G, int c, int i, int j, int k) {
   return pidx(G, c, ii[0], ii[1], ii[2]);
 }
 
+// Pusher of a species (Sec. 2.2: a conventional pusher, Boris 1970 or Vay
+// 2008, on the global Cartesian components; Sec. 5.2: optionally the hybrid
+// that hands particles over to the guiding-centre approximation).
+struct Pusher {
+  int vay = 0;              // 0: Boris, 1: Vay
+  int gca = 0;              // 1: guiding-centre hybrid
+  double e_ovr = 0.9;       // GCA only while |E| < e_ovr |B|
+  double larmor_max = 0.0;  // ... and the nominal gyroradius is below this length
+};
+
+// Guiding-centre regime test of the hybrid pusher (Sec. 5.2): the fields are
+// drift-dominated (|E| < e_ovr |B|) and the nominal gyroradius
+// rho_L = gamma beta m c^2 / (|q| B) = |u| m rho0 / (|q| |B|) = |u| dt / (2 |k| |B|)
+// is below the critical one.
+template <class T>
+bool gca_regime(double k, double dt, const T E[3], const T B[3], const T u[3], const Pusher &P) {
+  const double e2 = val(E[0]) * val(E[0]) + val(E[1]) * val(E[1]) + val(E[2]) * val(E[2]);
+  const double b2 = val(B[0]) * val(B[0]) + val(B[1]) * val(B[1]) + val(B[2]) * val(B[2]);
+  if (!(b2 > 0.0) || !(e2 < P.e_ovr * P.e_ovr * b2)) return false;
+  const double uabs = std::sqrt(val(u[0]) * val(u[0]) + val(u[1]) * val(u[1]) + val(u[2]) * val(u[2]));
+  const double rl = uabs * dt / (2.0 * std::fabs(k) * std::sqrt(b2));
+  return rl < P.larmor_max;
+}
+
+// Guiding-centre update with zero magnetic moment (reading of Sec. 5.2 after
+// Bacchini et al. 2020): the momentum perpendicular to B is dropped, the
+// parallel four-velocity takes the full parallel kick 2 k (E.b), and the
+// particle moves with its guiding centre, v = v_par b + E x B / B^2, whose
+// Lorentz factor is gamma = kappa sqrt(1 + u_par^2), kappa = (1 - v_E^2)^(-1/2);
+// u = u_par b + gamma v_E.
+template <class T>
+void gca_push(double k, const T E[3], const T B[3], T u[3]) {
+  T b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  T bn = d_sqrt(b2);
+  T b[3] = {B[0] / bn, B[1] / bn, B[2] / bn};
+  T vE[3] = {(E[1] * B[2] - E[2] * B[1]) / b2, (E[2] * B[0] - E[0] * B[2]) / b2,
+             (E[0] * B[1] - E[1] * B[0]) / b2};
+  T upar = u[0] * b[0] + u[1] * b[1] + u[2] * b[2] +
+           2.0 * k * (E[0] * b[0] + E[1] * b[1] + E[2] * b[2]);
+  T vE2 = vE[0] * vE[0] + vE[1] * vE[1] + vE[2] * vE[2];
+  T g = d_sqrt((1.0 + upar * upar) / (1.0 - vE2));
+  for (int a = 0; a < 3; ++a) u[a] = upar * b[a] + g * vE[a];
+}
+
+// Vay (2008) pusher: u^{n+1/2} = u^{n-1/2} + (q dt / m)(E + vbar x B) with
+// vbar the mean of the velocities before and after, solved in closed form
+// for the new Lorentz factor.  In code units (q dt / m) E = 2 k E and
+// (q dt / m)(v / 2) x B = k v x B.
+template <class T>
+void vay(double k, const T E[3], const T B[3], T u[3]) {
+  T g0 = d_sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  T v[3] = {u[0] / g0, u[1] / g0, u[2] / g0};
+  T up[3] = {u[0] + 2.0 * k * E[0] + k * (v[1] * B[2] - v[2] * B[1]),
+             u[1] + 2.0 * k * E[1] + k * (v[2] * B[0] - v[0] * B[2]),
+             u[2] + 2.0 * k * E[2] + k * (v[0] * B[1] - v[1] * B[0])};
+  T tau[3] = {k * B[0], k * B[1], k * B[2]};
+  T ustar = up[0] * tau[0] + up[1] * tau[1] + up[2] * tau[2];
+  T tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+  T sigma = 1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2] - tau2;
+  T gn = d_sqrt(0.5 * (sigma + d_sqrt(sigma * sigma + 4.0 * (tau2 + ustar * ustar))));
+  T t[3] = {tau[0] / gn, tau[1] / gn, tau[2] / gn};
+  T s = 1.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  T ut = up[0] * t[0] + up[1] * t[1] + up[2] * t[2];
+  T un[3] = {s * (up[0] + ut * t[0] + (up[1] * t[2] - up[2] * t[1])),
+             s * (up[1] + ut * t[1] + (up[2] * t[0] - up[0] * t[2])),
+             s * (up[2] + ut * t[2] + (up[0] * t[1] - up[1] * t[0]))};
+  for (int a = 0; a < 3; ++a) u[a] = un[a];
+}
+
 // one particle, one step (steps 3-8); hook(F6) lets the caller perturb F_p
 template <class T, class F, class Hook, class Dep>
 bool push_particle(const Grid &G, const F *EB, double dt, double q, double mass, double w,
-                   int cell[3], T d[3], T u[3], T &phi, Hook &&hook, Dep &&dep) {
+                   int cell[3], T d[3], T u[3], T &phi, Hook &&hook, Dep &&dep,
+                   const Pusher &P = Pusher()) {
   T Fp[6], E[3], B[3];
   interp(G, EB, cell, d, Fp);
   hook(Fp);
   to_cart(G, cell, d, phi, Fp, E, B);
   double k = q * dt / (2.0 * mass * G.rho0);
-  boris(k, E, B, u);
+  if (P.gca && gca_regime(k, dt, E, B, u, P))
+    gca_push(k, E, B, u);
+  else if (P.vay)
+    vay(k, E, B, u);
+  else
+    boris(k, E, B, u);
   MoveOut<T> o;
   move(G, dt, cell, d, phi, u, o);
   int cell_unwrapped_old[3] = {cell[0], cell[1], cell[2]};
@@ -911,12 +986,28 @@ void orc_move_literal(const orc_grid *g, double dt, int64_t n, const int32_t *ce
   }
 }
 
+void orc_vay(int64_t n, double k, const double *E3, const double *B3, double *u3) {
+  for (int64_t p = 0; p < n; ++p) vay(k, E3 + 3 * p, B3 + 3 * p, u3 + 3 * p);
+}
+
+void orc_gca(int64_t n, double k, const double *E3, const double *B3, double *u3) {
+  for (int64_t p = 0; p < n; ++p) gca_push(k, E3 + 3 * p, B3 + 3 * p, u3 + 3 * p);
+}
+
 void orc_sort_perm(int64_t n, const int32_t *keys, int32_t *perm) {
   std::vector<int32_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(),
                    [&](int32_t a, int32_t b) { return keys[a] < keys[b]; });
   std::copy(idx.begin(), idx.end(), perm);
+}
+
+int orc_sort_keys(const orc_grid *g, int64_t n, const int32_t *cell, const int32_t *alive,
+                  int32_t *keys) {
+  Grid G;
+  if (!make_grid(g, G)) return 1;
+  for (int64_t p = 0; p < n; ++p) keys[p] = sort_key(G, cell + 3 * p, alive[p]);
+  return 0;
 }
 
 // K steps of the particle step for every species (fields static).  Before step s
@@ -928,6 +1019,17 @@ void orc_sort_perm(int64_t n, const int32_t *keys, int32_t *perm) {
 int orc_run(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every, int64_t step0,
             const double *EB, int32_t nspecies, const double *q, const double *m,
             orc_species *sp, double *J) {
+  return orc_run_pushers(g, dt, nsteps, sort_every, step0, EB, nspecies, q, m, nullptr, nullptr,
+                         nullptr, sp, J);
+}
+
+// orc_run with a pusher per species: pusher[s] = 0 Boris, 1 Vay, +2 for the
+// guiding-centre hybrid with thresholds e_ovr[s], larmor_max[s] (NULL arrays:
+// Boris for every species).
+int orc_run_pushers(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every,
+                    int64_t step0, const double *EB, int32_t nspecies, const double *q,
+                    const double *m, const int32_t *pusher, const double *e_ovr,
+                    const double *larmor_max, orc_species *sp, double *J) {
   Grid G;
   if (!make_grid(g, G)) return 1;
   if (G.geom == 0)
@@ -973,9 +1075,16 @@ int orc_run(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every, in
         double *d = S.offs + 3 * p;
         double *u = S.u + 3 * p;
         double ph = (G.geom != 0 && S.phi) ? S.phi[p] : 0.0;
+        Pusher P;
+        if (pusher) {
+          P.vay = pusher[s] & 1;
+          P.gca = (pusher[s] >> 1) & 1;
+          P.e_ovr = e_ovr ? e_ovr[s] : 0.9;
+          P.larmor_max = larmor_max ? larmor_max[s] : 0.0;
+        }
         bool alive = push_particle(
             G, EBg.data(), dt, q[s], m[s], S.w[p], cell, d, u, ph, [](double *) {},
-            [&](int c, int i, int j, int k, double v) { J[jidx(G, c, i, j, k)] += v; });
+            [&](int c, int i, int j, int k, double v) { J[jidx(G, c, i, j, k)] += v; }, P);
         for (int dd = 0; dd < 3; ++dd) S.cell[3 * p + dd] = cell[dd];
         if (G.geom != 0 && S.phi) S.phi[p] = ph;
         S.alive[p] = alive ? 1 : 0;

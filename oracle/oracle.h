@@ -63,15 +63,24 @@ void orc_interp(const orc_grid *g, const double *EB, int64_t n, const int32_t *c
 void orc_to_cart(const orc_grid *g, int64_t n, const int32_t *cell, const double *offs,
                  const double *phi, const double *F6, double *E3, double *B3);
 void orc_boris(int64_t n, double k, const double *E3, const double *B3, double *u3);
+void orc_vay(int64_t n, double k, const double *E3, const double *B3, double *u3);
+void orc_gca(int64_t n, double k, const double *E3, const double *B3, double *u3);
 void orc_move(const orc_grid *g, double dt, int64_t n, int32_t *cell, double *offs,
               double *phi, const double *u3, int32_t *alive, int32_t *m3, double *dx3);
 void orc_move_literal(const orc_grid *g, double dt, int64_t n, const int32_t *cell,
                       const double *offs, const double *phi, const double *u3,
                       double *xnew, double *phinew);
 void orc_sort_perm(int64_t n, const int32_t *keys, int32_t *perm);
+/* the sort key of every particle (cell n x 3, alive n), as the sorts of orc_run form it */
+int orc_sort_keys(const orc_grid *g, int64_t n, const int32_t *cell, const int32_t *alive,
+                  int32_t *keys);
 int orc_run(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every,
             int64_t step0, const double *EB, int32_t nspecies, const double *q,
             const double *m, orc_species *sp, double *J);
+int orc_run_pushers(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every,
+                    int64_t step0, const double *EB, int32_t nspecies, const double *q,
+                    const double *m, const int32_t *pusher, const double *e_ovr,
+                    const double *larmor_max, orc_species *sp, double *J);
 int orc_adjoint(const orc_grid *g, double dt, int32_t K, const double *EB,
                 int32_t nspecies, const double *q, const double *m,
                 const orc_species *sp, const double *lamJ,

@@ -159,6 +159,26 @@ def boris(k, E, B, u):
     return u
 
 
+def vay(k, E, B, u):
+    """Vay (2008) push of u (n,3) with E, B (n,3); returns the new u."""
+    E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, 3)
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1, 3)
+    out = np.array(u, dtype=np.float64).reshape(-1, 3).copy()
+    lib().orc_vay(C.c_int64(out.shape[0]), C.c_double(k), _p(E, C.c_double), _p(B, C.c_double),
+                  _p(out, C.c_double))
+    return out
+
+
+def gca(k, E, B, u):
+    """Guiding-centre update of u (n,3); returns the new u."""
+    E = np.ascontiguousarray(E, dtype=np.float64).reshape(-1, 3)
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1, 3)
+    out = np.array(u, dtype=np.float64).reshape(-1, 3).copy()
+    lib().orc_gca(C.c_int64(out.shape[0]), C.c_double(k), _p(E, C.c_double), _p(B, C.c_double),
+                  _p(out, C.c_double))
+    return out
+
+
 def move(g, dt, cell, offs, phi, u):
     cell = np.array(cell, dtype=np.int32)
     offs = np.array(offs, dtype=np.float64)
@@ -193,6 +213,18 @@ def sort_perm(keys):
     perm = np.zeros(keys.shape[0], dtype=np.int32)
     lib().orc_sort_perm(C.c_int64(keys.shape[0]), _p(keys, C.c_int32), _p(perm, C.c_int32))
     return perm
+
+
+def sort_keys(g, cell, alive):
+    """The key every sort of run() orders a species by (int32 per particle)."""
+    cell = np.ascontiguousarray(cell, dtype=np.int32).reshape(-1, 3)
+    alive = np.ascontiguousarray(alive, dtype=np.int32).reshape(-1)
+    keys = np.zeros(cell.shape[0], dtype=np.int32)
+    rc = lib().orc_sort_keys(C.byref(g), C.c_int64(cell.shape[0]), _p(cell, C.c_int32),
+                             _p(alive, C.c_int32), _p(keys, C.c_int32))
+    if rc != 0:
+        raise RuntimeError(f"orc_sort_keys failed rc={rc}")
+    return keys
 
 
 def _species_struct(g, st, with_prev=False):
@@ -240,9 +272,16 @@ def run(g, dt, nsteps, EB, species, sort_every=0, step0=0):
     q = np.array([s["q"] for s in species], dtype=np.float64)
     m = np.array([s["m"] for s in species], dtype=np.float64)
     J = np.zeros((3,) + padded_shape(g))
-    rc = lib().orc_run(C.byref(g), C.c_double(dt), C.c_int32(nsteps), C.c_int32(sort_every),
-                       C.c_int64(step0), _p(EB, C.c_double), C.c_int32(len(structs)),
-                       _p(q, C.c_double), _p(m, C.c_double), arr, _p(J, C.c_double))
+    # pusher per species: "pusher" 0 Boris, 1 Vay, +2 guiding-centre hybrid
+    # with thresholds "e_ovr" and "larmor_max" (defaults: Boris)
+    push = np.array([int(s.get("pusher", 0)) for s in species], dtype=np.int32)
+    eov = np.array([float(s.get("e_ovr", 0.9)) for s in species], dtype=np.float64)
+    lmax = np.array([float(s.get("larmor_max", 0.0)) for s in species], dtype=np.float64)
+    rc = lib().orc_run_pushers(C.byref(g), C.c_double(dt), C.c_int32(nsteps),
+                               C.c_int32(sort_every), C.c_int64(step0), _p(EB, C.c_double),
+                               C.c_int32(len(structs)), _p(q, C.c_double), _p(m, C.c_double),
+                               _p(push, C.c_int32), _p(eov, C.c_double), _p(lmax, C.c_double),
+                               arr, _p(J, C.c_double))
     if rc != 0:
         raise RuntimeError(f"orc_run failed rc={rc}")
     out = []

@@ -284,6 +284,71 @@ def drho_nodes(n, dim, periodic_cart, prev, new, qw):
     return out
 
 
+def drho_nodes_fast(n, dim, periodic_cart, prev, new, qw):
+    """drho_nodes in FP64 with one bincount per stencil node, for tens of
+    millions of particles.  Every term is already proportional to a change
+    of weights (the telescoped product), so FP64 keeps the relative accuracy
+    of the charge change however small the displacements are."""
+    c0 = np.asarray(prev[0]).astype(np.int64)
+    a = np.asarray(prev[1], dtype=np.float64)
+    f = np.asarray(new[1], dtype=np.float64)
+    m = unwrap_step(prev[0], new[0], n, dim, periodic_cart)
+    N = c0.shape[0]
+    S0 = np.zeros((dim, 4, N))
+    S1 = np.zeros_like(S0)
+    D = np.zeros_like(S0)
+    for d in range(dim):
+        ad, fd, md = a[:, d], f[:, d], m[:, d]
+        S0[d, 1] = 1.0 - ad
+        S0[d, 2] = ad
+        for mv in (-1, 0, 1):
+            sel = md == mv
+            S1[d, 1 + mv, sel] = 1.0 - fd[sel]
+            S1[d, 2 + mv, sel] = fd[sel]
+        z, p1, mn = md == 0, md == 1, md == -1
+        D[d, 1, z] = ad[z] - fd[z]
+        D[d, 2, z] = fd[z] - ad[z]
+        D[d, 1, p1] = ad[p1] - 1.0
+        D[d, 2, p1] = (1.0 - fd[p1]) - ad[p1]
+        D[d, 3, p1] = fd[p1]
+        D[d, 0, mn] = 1.0 - fd[mn]
+        D[d, 1, mn] = (fd[mn] + ad[mn]) - 1.0
+        D[d, 2, mn] = -ad[mn]
+    qw = np.asarray(qw, dtype=np.float64)
+    shp = padded(n, dim)
+    size = int(np.prod(shp))
+    stride = (1, shp[2], shp[2] * shp[1])
+    out = np.zeros(size)
+    for combo in np.ndindex(*([4] * dim)):
+        dw = np.zeros(N)
+        for t in range(dim):
+            term = D[t, combo[t]].copy()
+            for d in range(dim):
+                if d < t:
+                    term *= S0[d, combo[d]]
+                elif d > t:
+                    term *= S1[d, combo[d]]
+            dw += term
+        if not np.any(dw):
+            continue
+        flat = np.zeros(N, dtype=np.int64)
+        for d in range(dim):
+            ii = c0[:, d] + combo[d] - 1
+            if periodic_cart:
+                ii = np.mod(ii, n[d])
+            flat += (ii + NG) * stride[d]
+        out += np.bincount(flat, weights=qw * dw, minlength=size)
+    return out.reshape(shp)
+
+
+def continuity_residual_telescoped(J, n, dim, periodic_cart, dt, prev, new, qw):
+    """continuity_residual over the whole lattice with the charge change of
+    drho_nodes_fast (FP64, no difference of large sums)."""
+    drho = drho_nodes_fast(n, dim, periodic_cart, prev, new, qw) / dt
+    res = np.asarray(divergence(J, n, dim, periodic_cart), dtype=np.float64) + drho
+    return float(np.sqrt(np.sum(res * res)) / np.sqrt(np.sum(drho * drho)))
+
+
 def continuity_residual_box(J, n, dim, periodic_cart, dt, prev, new, qw, box):
     """continuity_residual restricted to the nodes of box (a tuple of slices
     into the padded node array), with the charge change of the given

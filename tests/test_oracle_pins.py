@@ -597,3 +597,40 @@ def test_adjoint_matches_central_differences():
         fd = (loss(EB + h * vEB, sp_p) - loss(EB - h * vEB, sp_m)) / (2 * h)
         ip = np.sum(res["dEB"] * vEB) + sum(np.sum(a * b) for a, b in zip(res["du0"], vu))
         assert ip == pytest.approx(fd, rel=1e-6, abs=1e-8)
+
+
+def test_sort_keys_export_orders_like_run():
+    """The exported key function orders particles exactly as the sorts of a
+    run do (the per-step GPU tests sort the GPU's own state with it)."""
+    rng = np.random.default_rng(21)
+    n = (12, 9, 7)
+    g = O.make_grid("cart", 3, n, (0, 0, 0), n)
+    P = 3000
+    cell = np.stack([rng.integers(0, n[d], P) for d in range(3)], 1).astype(np.int32)
+    alive = (rng.random(P) > 0.1).astype(np.int32)
+    sp = [dict(q=1.0, m=1.0, cell=cell, offs=rng.random((P, 3)), u=np.zeros((P, 3)),
+               w=np.ones(P), phi=None, alive=alive)]
+    out, _ = O.run(g, 0.1, 1, np.zeros((6,) + O.padded_shape(g)), sp, sort_every=1)
+    np.testing.assert_array_equal(O.sort_perm(O.sort_keys(g, cell, alive)), out[0]["perm"])
+
+
+@pytest.mark.parametrize("geom,dim,n,vt", [("cart", 2, (6, 5, 1), 0.0), ("cart", 3, (5, 4, 3), 0.0),
+                                           ("qsph", 2, (12, 10, 1), 0.3)])
+def test_fast_telescoped_continuity_checker(geom, dim, n, vt):
+    """The FP64 bincount form of the telescoped charge change equals the
+    extended-precision one, and gives a residual at round-off for the
+    reference's own step."""
+    rng = np.random.default_rng(12)
+    g, cell, offs, u, phi, q, w = _random_state(geom, dim, n, 400, rng, vt=vt)
+    EB = rng.normal(size=(6,) + O.padded_shape(g)) * 0.3
+    dt = O.dt_from_cfl(g, 0.45)
+    sp = [dict(q=1.0, m=1.0, cell=cell, offs=offs, u=u, w=w * q, phi=phi,
+               alive=np.ones(len(w), np.int32))]
+    out, J = O.run(g, dt, 1, EB, sp)
+    s = out[0]
+    prev, new = (s["cell_prev"], s["offs_prev"]), (s["cell"], s["offs"])
+    a = checks.drho_nodes(n, dim, geom == "cart", prev, new, s["w"])
+    b = checks.drho_nodes_fast(n, dim, geom == "cart", prev, new, s["w"])
+    assert np.max(np.abs(np.asarray(a, dtype=np.float64) - b)) <= 1e-14 * np.max(np.abs(b))
+    r = checks.continuity_residual_telescoped(J, n, dim, geom == "cart", dt, prev, new, s["w"])
+    assert r < 1e-12, r
