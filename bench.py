@@ -61,7 +61,10 @@ def measured_traffic(kernel_key):
         return None
 
 
-def run_gpu(wl, prec, steps, warmup, log):
+def run_gpu(wl, prec, steps, warmup, log, repeats=5):
+    """warmup untimed steps, then `repeats` timed runs of exactly `steps`
+    steps each (HIP events on the library's stream, synchronized around each
+    run); the reported figures are those of the median run."""
     import torch
 
     from paper_2511_17710_amd import picstep as P
@@ -69,31 +72,92 @@ def run_gpu(wl, prec, steps, warmup, log):
     ctx = P.from_workload(wl, prec=prec, sort_every=wl.sort_every)
     dt = ctx.timestep_from_cfl(wl.cfl)
     torch.cuda.synchronize()
-    log(f"[bench] {prec}: loaded {wl.nparticles} particles in {time.time() - t0:.1f}s, dt={dt:.6g}")
+    log(f"[bench] {wl.name} {prec}: loaded {wl.nparticles} particles in {time.time() - t0:.1f}s, "
+        f"dt={dt:.6g}")
     ctx.push_deposit(dt, warmup)
     torch.cuda.synchronize()
-    ctx.timing_enable(True)
     s = ctx.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(s)
-    ctx.push_deposit(dt, steps)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    tm = ctx.timing_read()
-    ctx.timing_enable(False)
     n = wl.nparticles
-    res = dict(ms_per_step=ms / steps, ns_per_particle_step=ms * 1e6 / (n * steps),
-               push_ms_avg=tm["push_ms"] / max(tm["push_launches"], 1),
-               push_launches=tm["push_launches"], sort_ms_total=tm["sort_ms"],
-               sort_calls=tm["sort_calls"],
-               global_deposits_per_block=round(tm["push_global_particles"] / max(tm["push_blocks"], 1), 5))
-    log(f"[bench] {prec}: {res}")
+    runs = []
+    for _ in range(repeats):
+        ctx.timing_enable(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        ctx.push_deposit(dt, steps)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        tm = ctx.timing_read()
+        ctx.timing_enable(False)
+        runs.append(dict(ms=ms, push_ms_avg=tm["push_ms"] / max(tm["push_launches"], 1),
+                         push_launches=tm["push_launches"], sort_ms_total=tm["sort_ms"],
+                         sort_calls=tm["sort_calls"],
+                         global_deposits_per_block=round(
+                             tm["push_global_particles"] / max(tm["push_blocks"], 1), 5)))
+    med = sorted(runs, key=lambda r: r["ms"])[len(runs) // 2]
+    res = dict(ms_per_step=med["ms"] / steps, ns_per_particle_step=med["ms"] * 1e6 / (n * steps),
+               push_ms_avg=med["push_ms_avg"], push_launches=med["push_launches"],
+               sort_ms_total=med["sort_ms_total"], sort_calls=med["sort_calls"],
+               global_deposits_per_block=med["global_deposits_per_block"],
+               repeats_ns_per_particle_step=[round(r["ms"] * 1e6 / (n * steps), 5) for r in runs])
+    log(f"[bench] {wl.name} {prec}: {res}")
     del ctx
     torch.cuda.empty_cache()
     return res
+
+
+def kernel_roofline_meta(meta, prec, r):
+    """Algorithmic bytes of one launch of the fused step kernel over its
+    average HIP-event duration, against the HBM peak."""
+    n = meta["particles"]
+    bpp = algorithmic_bytes_per_particle(meta["dim"], prec, meta["ncells"], n,
+                                         meta["geom"] != "cart")
+    ach = bpp * n / (r["push_ms_avg"] * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_particle=round(bpp, 3),
+                kernel_ms_avg=round(r["push_ms_avg"], 4))
+
+
+def kernel_roofline(wl, prec, r):
+    return kernel_roofline_meta(dict(particles=wl.nparticles, dim=wl.dim, geom=wl.geom,
+                                     ncells=int(np.prod(wl.n[:wl.dim]))), prec, r)
+
+
+def particle_sweep(wl, fractions, steps, warmup, log):
+    """FP32 per-particle cost at fixed grid and fields for a random subset of
+    every species (the particle-count dependence of the paper's Sec. 4)."""
+    import copy
+    rng = np.random.default_rng(4)
+    out = []
+    for f in fractions:
+        sub = copy.copy(wl)
+        sub.species = []
+        for sp in wl.species:
+            n = sp["cell"].shape[0]
+            k = max(1, int(round(f * n)))
+            pick = np.sort(rng.choice(n, size=k, replace=False)) if k < n else np.arange(n)
+            sub.species.append({key: (v[pick] if isinstance(v, np.ndarray) else v)
+                                for key, v in sp.items()})
+        r = run_gpu(sub, "f32", steps, warmup, log, repeats=3)
+        out.append(dict(fraction=f, particles=sub.nparticles,
+                        ns_per_particle_step=round(r["ns_per_particle_step"], 5),
+                        push_ms_avg=round(r["push_ms_avg"], 4)))
+    return out
+
+
+def adjoint_kernel_bytes_per_particle(dim, prec, ncells, nparticles):
+    """Minimum HBM traffic of one reverse-step kernel launch per particle:
+    the stored state read (cell, offsets, u, w), the momentum and offset
+    adjoints read and written, the fields read and dL/d(fields)
+    read-modify-written once per cell (dL/dJ, read on the last step only, is
+    left out)."""
+    b = 4 if prec == "f32" else 8
+    state = 4 + dim * b + 3 * b + b
+    lam = 2 * (3 * b + dim * b)
+    grid = (6 * b + 2 * 6 * b) * ncells / nparticles
+    return state + lam + grid
 
 
 def run_adjoint(prec, log, name="cart3d_64_adj"):
@@ -123,10 +187,16 @@ def run_adjoint(prec, log, name="cart3d_64_adj"):
     torch.cuda.synchronize()
     tm = ctx.timing_read()
     n = wl.nparticles
+    kms = tm["adjoint_ms"] / max(tm["adjoint_launches"], 1)
+    bpp = adjoint_kernel_bytes_per_particle(wl.dim, prec, int(np.prod(wl.n[:wl.dim])), n)
+    ach = bpp * n / (kms * 1e-3) / 1e9
     res = dict(workload=wl.name, particles=n, K=K, checkpoint_every=m, sort_every=wl.sort_every,
                forward_ns_per_particle_step=e[0].elapsed_time(e[1]) * 1e6 / (n * K),
                backward_ns_per_particle_step=e[1].elapsed_time(e[2]) * 1e6 / (n * K),
-               adjoint_kernel_ms_avg=tm["adjoint_ms"] / max(tm["adjoint_launches"], 1),
+               adjoint_kernel_ms_avg=kms,
+               roofline=dict(kernel="k_adjoint<0,3,%s>" % ("float" if prec == "f32" else "double"),
+                             bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_particle=round(bpp, 3)),
                grad_norm=float(dEB.double().norm()))
     log(f"[bench] adjoint {prec}: {res}")
     del ctx
@@ -161,12 +231,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--workload", default="cart3d_128")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--skip-adjoint", action="store_true")
+    ap.add_argument("--skip-axisymmetric", action="store_true",
+                    help="leave out the 1024x512 and 2048x1024 axisymmetric rows")
+    ap.add_argument("--skip-sweep", action="store_true",
+                    help="leave out the particle-count sweep on the default grid")
     ap.add_argument("--sort-every", type=int, default=None,
                     help="override the workload's sort cadence (steps)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -189,8 +264,6 @@ def main():
     if args.sort_every is not None:
         wl.sort_every = args.sort_every
     log(f"[bench] inputs {wl.name}: {wl.nparticles} particles in {time.time() - t0:.1f}s")
-    ncells = int(np.prod(wl.n[:wl.dim]))
-    has_phi = wl.geom != "cart"
 
     if args.calib_copy_mb:
         nb = args.calib_copy_mb << 20
@@ -201,17 +274,51 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy_mb} MiB done")
 
-    r32 = run_gpu(wl, "f32", args.steps, args.warmup, log)
-    r64 = None if args.skip_fp64 else run_gpu(wl, "f64", args.steps, args.warmup, log)
+    r32 = run_gpu(wl, "f32", args.steps, args.warmup, log, args.repeats)
+    r64 = None if args.skip_fp64 else run_gpu(wl, "f64", args.steps, args.warmup, log,
+                                              args.repeats)
+    sweep = None
+    if not args.skip_sweep and wl.name == "cart3d_128":
+        sweep = particle_sweep(wl, (0.01, 0.03, 0.1, 0.3), args.steps, args.warmup, log)
     cpu = None if args.skip_cpu else cpu_baseline(wl, args.cpu_sample, args.cpu_steps, log)
+    meta = dict(name=wl.name, dim=wl.dim, geom=wl.geom, grid=list(wl.n[:wl.dim]),
+                ncells=int(np.prod(wl.n[:wl.dim])), particles=wl.nparticles,
+                species=len(wl.species), sort_every=wl.sort_every, cfl=wl.cfl)
+    del wl  # release the default workload's host arrays before the next ones
+    axi = {}
+    if not args.skip_axisymmetric and args.workload == "cart3d_128":
+        for name in ("qsph_1024x512", "qsph_2048x1024"):
+            w2 = W.by_name(name)
+            row = {"particles": w2.nparticles, "grid": list(w2.n[:w2.dim]),
+                   "sort_every": w2.sort_every}
+            for prec in (("f32",) if args.skip_fp64 else ("f32", "f64")):
+                r = run_gpu(w2, prec, args.steps, args.warmup, log, args.repeats)
+                row[prec] = dict(ns_per_particle_step=round(r["ns_per_particle_step"], 5),
+                                 ms_per_step=round(r["ms_per_step"], 4),
+                                 repeats_ns_per_particle_step=r["repeats_ns_per_particle_step"],
+                                 roofline=kernel_roofline(w2, prec, r))
+            if "f64" in row:
+                row["fp32_vs_fp64_speedup"] = round(
+                    row["f64"]["ns_per_particle_step"] / row["f32"]["ns_per_particle_step"], 3)
+            axi[name] = row
+            del w2
     adj = None
     if not args.skip_adjoint:
         adj = {p: run_adjoint(p, log) for p in (("f32",) if args.skip_fp64 else ("f32", "f64"))}
+    emit(args, meta, dict(r32=r32, r64=r64, sweep=sweep, cpu=cpu, axi=axi, adj=adj))
 
-    n = wl.nparticles
-    bpp32 = algorithmic_bytes_per_particle(wl.dim, "f32", ncells, n, has_phi)
-    ach = bpp32 * n / (r32["push_ms_avg"] * 1e-3) / 1e9
-    kname = "k_push<%d,%d,float>" % ({"cart": 0, "sph": 1, "qsph": 2}[wl.geom], wl.dim)
+
+def emit(args, meta, f):
+    r32, r64 = f["r32"], f["r64"]
+    n = meta["particles"]
+    roof = kernel_roofline_meta(meta, "f32", r32)
+    traffic = measured_traffic(f"k_push_{meta['name']}") if meta["name"] == "cart3d_128" else None
+    roof.update({"traffic": traffic,
+                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                 "traffic_GBs": (round(traffic / (r32["push_ms_avg"] * 1e-3) / 1e9, 1)
+                                 if traffic else None),
+                 "kernel": "k_push<%d,%d,float>" % ({"cart": 0, "sph": 1, "qsph": 2}[meta["geom"]],
+                                                    meta["dim"])})
     out = {
         "metric": "ns/particle/step push+deposit (fwd, adjoint) FP32 vs FP64; HBM GB/s vs peak",
         "value": round(r32["ns_per_particle_step"], 5),
@@ -225,28 +332,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "grid": list(wl.n[:wl.dim]), "particles": n,
-                   "species": len(wl.species), "sort_every": wl.sort_every, "cfl": wl.cfl,
-                   "offsets": "u32 fixed point (f32 build)"},
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": (measured_traffic(f"k_push_{wl.name}")
-                                 if wl.name == "cart3d_128" else None),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": kname,
-                     "bytes_per_particle": round(bpp32, 3),
-                     "kernel_ms_avg": round(r32["push_ms_avg"], 4)},
+        "config": {"workload": meta["name"], "grid": meta["grid"], "particles": n,
+                   "species": meta["species"], "sort_every": meta["sort_every"],
+                   "cfl": meta["cfl"], "offsets": "u32 fixed point (f32 build)",
+                   "repeats": args.repeats, "value_is": "median of the repeats"},
+        "roofline": roof,
         "fp32": r32,
     }
     if r64:
-        bpp64 = algorithmic_bytes_per_particle(wl.dim, "f64", ncells, n, has_phi)
-        r64["achieved_GBs"] = round(bpp64 * n / (r64["push_ms_avg"] * 1e-3) / 1e9, 1)
+        r64["roofline"] = kernel_roofline_meta(meta, "f64", r64)
         out["fp64"] = r64
         out["fp32_vs_fp64_speedup"] = round(r64["ns_per_particle_step"] / r32["ns_per_particle_step"], 3)
-    if adj:
-        out["adjoint"] = adj
-    if cpu:
-        out["cpu_baseline"] = cpu
+    if f["axi"]:
+        out["axisymmetric"] = f["axi"]
+    if f["sweep"]:
+        out["particle_sweep_fp32"] = f["sweep"] + [dict(fraction=1.0, particles=n,
+                                                        ns_per_particle_step=round(r32["ns_per_particle_step"], 5),
+                                                        push_ms_avg=round(r32["push_ms_avg"], 4))]
+    if f["adj"]:
+        out["adjoint"] = f["adj"]
+    if f["cpu"]:
+        out["cpu_baseline"] = f["cpu"]
     print(json.dumps(out), flush=True)
 
 

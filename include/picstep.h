@@ -179,6 +179,30 @@ pic_status pic_timestep_from_cfl(const pic_ctx *ctx, double cfl, double *dt);
 pic_status pic_species_add(pic_ctx *ctx, double charge, double mass, uint64_t capacity,
                            int32_t *species_id);
 
+/* Pushers of the momentum update (step 5).  The method leaves the choice to a
+ * conventional pusher on the global Cartesian components (Sec. 2.2, citing
+ * Boris 1970 and Vay 2008); for strongly magnetised plasma it adds a hybrid
+ * that hands a particle over to the guiding-centre approximation (Sec. 5.2,
+ * after Bacchini et al. 2020). */
+typedef enum {
+  PIC_PUSH_BORIS = 0, /* relativistic Boris rotation (default) */
+  PIC_PUSH_VAY = 1,   /* Vay (2008): implicit mean velocity, solved in closed form */
+  PIC_PUSH_GCA = 2    /* flag, with either: the guiding-centre hybrid */
+} pic_pusher;
+
+/* Sets the pusher of a species (default PIC_PUSH_BORIS).  With PIC_PUSH_GCA a
+ * particle is advanced as its guiding centre on a step where |E| < e_ovr |B|
+ * (0 < e_ovr < 1) and its nominal gyroradius |u| m rho0 / (|q| |B|) is below
+ * larmor_max (> 0, code length units): its momentum across B is dropped, the
+ * parallel four-velocity takes the full parallel kick, and it drifts with
+ * E x B / B^2.  The regime test is taken in FP64 on the particle's fields and
+ * momentum before the step.  e_ovr and larmor_max are ignored without the
+ * flag.  PIC_E_ARG for an unknown pusher or bad thresholds.  The adjoint
+ * entry points refuse (PIC_E_UNSUPPORTED) a context with a species that does
+ * not use the Boris pusher.  Host only. */
+pic_status pic_species_set_pusher(pic_ctx *ctx, int32_t species, int32_t pusher, double e_ovr,
+                                  double larmor_max);
+
 /* Sets the fields from a host FP64 array in `basis`.  Tetrad input is turned
  * into contravariant components F^i = F^i_hat / sqrt(h_ii) at each
  * component's own Yee point (eq. curvspace-tetradtrans), in FP64, then
@@ -308,13 +332,14 @@ pic_status pic_checkpoint_load(pic_ctx *ctx, const void *slot);
 typedef struct {
   void *lam_u;     /* device [3][capacity] real: in dL/du after the step, out dL/du before */
   void *lam_offs;  /* device [3][capacity] real: likewise for the in-cell offsets (rows of
-                      unused dimensions are left untouched) */
+                      unused dimensions are left untouched, except that on (quasi-)spherical
+                      grids row 2 carries dL/dphi, the adjoint of the azimuth) */
   void *dEB;       /* device [6][npts] real: the step's dL/d(fields) is added, periodic
                       ghost contributions folded into their images */
   void *lamJ_work; /* device [3][npts] real scratch, used when lamJ is given */
 } pic_adjoint_buffers;
 
-/* Reverse of one particle step (Cartesian grids) from the current particle
+/* Reverse of one particle step from the current particle
  * state, the state before that step (e.g. just restored with
  * pic_checkpoint_load): lamJ (device [3][npts] real, dL/dJ of this step, may
  * be NULL) is gathered through the step's zig-zag, the adjoints of u and of

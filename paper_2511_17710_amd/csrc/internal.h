@@ -63,6 +63,9 @@ struct SpeciesTable {
   int64_t blk0[MAXSP + 1]; // prefix of block counts over species
   double k[MAXSP];         // q dt / (2 m rho0)
   double qdt[MAXSP];       // q / dt
+  int pusher[MAXSP];       // 0 Boris, 1 Vay, +2 guiding-centre hybrid
+  double gca_e_ovr[MAXSP]; // hybrid: guiding centre while |E| < e_ovr |B| ...
+  double gca_larmor[MAXSP];  // ... and the nominal gyroradius is below this length
 };
 
 template <class Real>

@@ -1,10 +1,13 @@
-// k_adjoint.hip -- reverse-mode derivative of one particle step (Cartesian
-// grids), written by hand: the forward step of the particle is recomputed in
-// registers from its stored state, then the adjoints are propagated backwards
-// through the zig-zag deposit (a gather of dL/dJ), the move, the Boris push
-// and the interpolation (a scatter into dL/dE, dL/dB).  Discrete branches
-// (cell crossings, the relay clamp, the half-cell stagger choice) take the
-// derivative of the branch the forward step took.
+// k_adjoint.hip -- reverse-mode derivative of one particle step, written by
+// hand, on Cartesian and axisymmetric (spherical, quasi-spherical) grids: the
+// forward step of the particle is recomputed in registers from its stored
+// state, then the adjoints are propagated backwards through the zig-zag
+// deposit (a gather of dL/dJ), the move (on axisymmetric grids the
+// offset-relative back-transform, its azimuth step and the position
+// dependence of the metric), the Boris push, the tetrad and rotation, and
+// the interpolation (a scatter into dL/dE, dL/dB).  Discrete branches (cell
+// crossings, the relay clamp, the half-cell stagger choice, the theta clamp)
+// take the derivative of the branch the forward step took.
 #include "block_util.h"
 #include "step_device.h"
 
@@ -29,8 +32,9 @@ __device__ __forceinline__ void corners(const Real *__restrict__ A, int base, in
 
 // copy ncomp components of a padded global array over the box [o, o + s) of
 // (unwrapped) cells into LDS, component-major, x fastest; Cartesian grids
-// take the periodic image of points outside the padded lattice
-template <int DIM, class Real>
+// take the periodic image of points outside the padded lattice, curvilinear
+// grids read them as zero (no particle stencil reaches them)
+template <int GEOM, int DIM, class Real>
 __device__ __forceinline__ void stage_box(const GridConst &g, const Real *__restrict__ src,
                                           int ncomp, const int o[3], const int sz3[3],
                                           Real *dst) {
@@ -51,15 +55,294 @@ __device__ __forceinline__ void stage_box(const GridConst &g, const Real *__rest
     tile_for_each<16, Real>(
         ncomp, DIM == 3 ? 2 : 1, sz3[0], sz3[1], sz3[2],
         [&](int ix, int iy) {
-          const int gx = wrap_periodic(o[0] + ix, g.n[0]);
-          const int gy = (DIM == 3) ? wrap_periodic(o[1] + iy, g.n[1]) : 0;
-          return PlanePt{(gx + NG) + ((DIM == 3) ? g.np[0] * (gy + NG) : 0), true};
+          int gx = o[0] + ix, gy = (DIM == 3) ? o[1] + iy : 0;
+          bool ok = true;
+          if (GEOM == 0) {
+            gx = wrap_periodic(gx, g.n[0]);
+            if (DIM == 3) gy = wrap_periodic(gy, g.n[1]);
+          } else {
+            ok = gx >= -NG && gx < g.n[0] + NG;
+          }
+          return PlanePt{(gx + NG) + ((DIM == 3) ? g.np[0] * (gy + NG) : 0), ok};
         },
         [&](const PlanePt &pp, int, int comp, int w) {
-          return src[comp * npts + pp.off + wstride * (wrap_periodic(o[WA] + w, g.n[WA]) + NG)];
+          int gw = o[WA] + w;
+          bool ok = pp.ok;
+          if (GEOM == 0)
+            gw = wrap_periodic(gw, g.n[WA]);
+          else
+            ok = ok && gw >= -NG && gw < g.n[WA] + NG;
+          return ok ? src[comp * npts + pp.off + wstride * (gw + NG)] : (Real)0;
         },
         [&](const PlanePt &, int x, int, int, Real v) { dst[x] = v; });
   }
+}
+
+// A padded global array or a block's LDS copy of it over a box: component c,
+// cell (I, J, K) (unwrapped) at c*cs + (I - o0) + sy*(J - o1) + sz*(K - o2).
+template <class Real>
+struct BoxView {
+  const Real *L;
+  int cs, sy, sz;
+  int o[3];
+};
+
+// Reverse of step 8: dL/dJ gathered through the particle's zig-zag.  za: old
+// offsets, zb: new offsets + m (both exact, measured from the old cell i0).
+// Adds dL/d(old offset) into ab and dL/d(displacement) into dxb (b = a +
+// displacement), dL/d(dx3) (2D out-of-plane displacement) into dx3b; bfix[d]:
+// the new position is a constant in dimension d (theta clamp), so nothing
+// flows through b there.
+template <int DIM, class Real>
+__device__ __forceinline__ void zigzag_rev(const BoxView<Real> &V, const int i0[3], const int m[3],
+                                           const double za[3], const double zb[3], Real C,
+                                           Real dx3, const bool bfix[3], Real ab[3], Real dxb[3],
+                                           Real &dx3b) {
+  Real Fs[2][3] = {{0, 0, 0}, {0, 0, 0}}, Ws[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  bool mid_free[3] = {false, false, false};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double lo = (double)(min(0, m[a]) + 1), hi = (double)max(0, m[a]);
+    const double mid = (za[a] + zb[a]) * 0.5;
+    const double xr = fmin(lo, fmax(hi, mid));
+    mid_free[a] = (mid >= hi) && (mid <= lo);
+    Fs[0][a] = (Real)(xr - za[a]);
+    Fs[1][a] = (Real)(zb[a] - xr);
+    Ws[0][a] = (Real)((za[a] + xr) * 0.5);
+    Ws[1][a] = (Real)((xr + zb[a]) * 0.5 - (double)m[a]);
+  }
+  Real Fb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Wb[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  const Real *L = V.L;
+  const int cs = V.cs, sy = V.sy, sz = V.sz;
+#pragma unroll
+  for (int sg = 0; sg < 2; ++sg) {
+    const int I = i0[0] + (sg ? m[0] : 0), Jc = i0[1] + (sg ? m[1] : 0);
+    const int K = (DIM == 3) ? i0[2] + (sg ? m[2] : 0) : 0;
+    const int base = (I - V.o[0]) + sy * (Jc - V.o[1]) + ((DIM == 3) ? sz * (K - V.o[2]) : 0);
+    const Real Fx = Fs[sg][0], Fy = Fs[sg][1], Wx = Ws[sg][0], Wy = Ws[sg][1];
+    if (DIM == 2) {
+      const Real l10 = L[base], l11 = L[base + sy];
+      const Real l20 = L[cs + base], l21 = L[cs + base + 1];
+      Fb[sg][0] += C * (l10 * ((Real)1 - Wy) + l11 * Wy);
+      Wb[sg][1] += C * Fx * (l11 - l10);
+      Fb[sg][1] += C * (l20 * ((Real)1 - Wx) + l21 * Wx);
+      Wb[sg][0] += C * Fy * (l21 - l20);
+      const Real *L3 = L + 2 * cs + base;
+      const Real a00 = L3[0], a10 = L3[1], a01 = L3[sy], a11 = L3[sy + 1];
+      const Real h = C * dx3 * (Real)0.5;
+      const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
+      const Real val = a00 * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy) +
+                       a10 * (Wx * ((Real)1 - Wy) - cxy) + a01 * (((Real)1 - Wx) * Wy - cxy) +
+                       a11 * (Wx * Wy + cxy);
+      dx3b += C * (Real)0.5 * val;
+      Wb[sg][0] += h * (-a00 * ((Real)1 - Wy) + a10 * ((Real)1 - Wy) - a01 * Wy + a11 * Wy);
+      Wb[sg][1] += h * (-a00 * ((Real)1 - Wx) - a10 * Wx + a01 * ((Real)1 - Wx) + a11 * Wx);
+      const Real csum = (a00 - a10 - a01 + a11) * h * (Real)(1.0 / 12.0);
+      Fb[sg][0] += csum * Fy;
+      Fb[sg][1] += csum * Fx;
+    } else {
+      // component c with transverse dims (a, b): value = C F_c (w_a w_b + sgn F_a F_b / 12)
+#pragma unroll
+      for (int comp = 0; comp < 3; ++comp) {
+        const int da = (comp == 0) ? 1 : 0;
+        const int db = (comp == 2) ? 1 : 2;
+        const int sa = (da == 0) ? 1 : sy;
+        const int sb = (db == 1) ? sy : sz;
+        const Real *Lc = L + comp * cs + base;
+        const Real l00 = Lc[0], l10 = Lc[sa], l01 = Lc[sb], l11 = Lc[sa + sb];
+        const Real Fc = Fs[sg][comp];
+        const Real Wa = Ws[sg][da], Wbb = Ws[sg][db];
+        const Real Fa = Fs[sg][da], Fbt = Fs[sg][db];
+        const Real ga = (Real)1 - Wa, gb = (Real)1 - Wbb;
+        const Real cab = Fa * Fbt * (Real)(1.0 / 12.0);
+        const Real sgn = l00 - l10 - l01 + l11;
+        const Real val = l00 * (ga * gb + cab) + l10 * (Wa * gb - cab) + l01 * (ga * Wbb - cab) +
+                         l11 * (Wa * Wbb + cab);
+        Fb[sg][comp] += C * val;
+        Wb[sg][da] += C * Fc * (-l00 * gb + l10 * gb - l01 * Wbb + l11 * Wbb);
+        Wb[sg][db] += C * Fc * (-l00 * ga - l10 * Wa + l01 * ga + l11 * Wa);
+        Fb[sg][da] += C * Fc * sgn * Fbt * (Real)(1.0 / 12.0);
+        Fb[sg][db] += C * Fc * sgn * Fa * (Real)(1.0 / 12.0);
+      }
+    }
+  }
+  // relay: F1 = xr - a, F2 = b - xr, W1 = (a + xr)/2, W2 = (xr + b)/2 - m
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const Real xrb = Fb[0][a] - Fb[1][a] + (Real)0.5 * (Wb[0][a] + Wb[1][a]);
+    Real abar = -Fb[0][a] + (Real)0.5 * Wb[0][a];
+    Real bbar = Fb[1][a] + (Real)0.5 * Wb[1][a];
+    if (mid_free[a]) {  // xr = (a + b)/2
+      abar += (Real)0.5 * xrb;
+      bbar += (Real)0.5 * xrb;
+    }
+    if (bfix[a]) bbar = 0;
+    // b = a + displacement
+    ab[a] += abar + bbar;
+    dxb[a] += bbar;
+  }
+}
+
+// Per-particle reverse on a Cartesian grid: forward recompute (tetrad =
+// cell sizes, Boris, move), then the reverse of deposit, move and Boris.
+// Returns dL/d(interpolated F) in Fb and adds dL/d(old offsets) (except the
+// interpolation weights' part) into ab; writes dL/du before the step.
+template <int DIM, class Real>
+__device__ __forceinline__ void cart_particle_rev(const AdjArgs<Real> &A, int s, int64_t p,
+                                                  const int i[3], const OffT<Real> q[3],
+                                                  const Real F[6], const BoxView<Real> &LJ,
+                                                  Real Fb[6], Real ab[3]) {
+  using PS = Pos<Real>;
+  const GridConst &g = A.g;
+  const Real u0[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
+  const Real k = (Real)A.sp.k[s];
+  const Real dtr = (Real)A.dt;
+  Real E[3], B[3], sc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sc[a] = (a < DIM) ? (Real)g.dx[a] : (Real)1;
+    E[a] = F[a] * sc[a];
+    B[a] = F[3 + a] * sc[a];
+  }
+  Real un[3] = {u0[0], u0[1], u0[2]};
+  BorisRec<Real> R;
+  boris_rec(k, E, B, un, R);
+  // steps 6-7: move, as in the forward kernel
+  const Real ig = rsqrt_r((Real)1 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+  int m[3] = {0, 0, 0};
+  double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const Real dx = cart_disp(g, a, dtr, un[a], ig);
+    OffT<Real> qn;
+    m[a] = PS::move(q[a], (double)dx, qn);
+    za[a] = PS::exact(q[a]);
+    zb[a] = PS::exact(qn) + (double)m[a];
+  }
+  // the adjoint of the new offsets passes to the old offset and the displacement
+  Real dxb[3] = {0, 0, 0}, dx3b = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const Real l = A.lam_d[a][p];
+    ab[a] += l;
+    dxb[a] += l;
+  }
+  if (A.lamJ) {
+    const bool bfix[3] = {false, false, false};
+    const Real dx3 = (DIM == 2) ? dtr * un[2] * ig : (Real)0;
+    zigzag_rev<DIM, Real>(LJ, i, m, za, zb, (Real)A.sp.qdt[s] * A.p.w[p], dx3, bfix, ab, dxb, dx3b);
+  }
+  // steps 6-7 reversed: dx_a = dt u_a / (gamma Delta_a); 2D also dx3 = dt u_z / gamma
+  Real wv[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) wv[a] = dxb[a] * dtr / (Real)g.dx[a];
+  if (DIM == 2) wv[2] = dx3b * dtr;
+  const Real uw = un[0] * wv[0] + un[1] * wv[1] + un[2] * wv[2];
+  Real unb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) unb[a] = A.lam_u[a][p] + wv[a] * ig - un[a] * uw * ig * ig * ig;
+  Real ub[3], Eb[3], Bb[3];
+  boris_rev(k, R, unb, ub, Eb, Bb);
+  // tetrad reversed
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fb[a] = Eb[a] * sc[a];
+    Fb[3 + a] = Bb[a] * sc[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.lam_u[a][p] = ub[a];
+}
+
+// Per-particle reverse on an axisymmetric grid, with the metric, rotation
+// and move in CT (FP64 near the axis and r_min in FP32 builds, as in the
+// forward step).  D: the offsets as the forward step feeds them to the
+// metric.  dL/dphi lives in lam_phi.
+template <int GEOM, class CT, class Real, class D>
+__device__ __forceinline__ void axi_particle_rev(const AdjArgs<Real> &A, int s, int64_t p,
+                                                 const int i[3], const OffT<Real> q[3], D d1,
+                                                 D d2, const Real F[6], const BoxView<Real> &LJ,
+                                                 Real Fb[6], Real ab[3]) {
+  using PS = Pos<Real>;
+  const GridConst &g = A.g;
+  const Real k = (Real)A.sp.k[s];
+  const Real phi = A.p.phi[p];
+  // ---- forward recompute (the operations of axi_particle)
+  const CT x1 = (CT)i[0] + (CT)d1;
+  const CT x2 = (CT)i[1] + (CT)d2;
+  const AxiMetric<CT> M = axi_metric<GEOM, CT>(g, x1, x2);
+  CT sp, cp;
+  sincos_r((CT)phi, &sp, &cp);
+  Real E[3], B[3];
+  axi_to_cart<CT, Real>(M, sp, cp, F, E, B);
+  Real un[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
+  BorisRec<Real> R;
+  boris_rec(k, E, B, un, R);
+  const CT uu[3] = {(CT)un[0], (CT)un[1], (CT)un[2]};
+  const CT gi = rsqrt_r((CT)1 + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]);
+  const CT dtg = (CT)A.dt * gi;
+  const CT DX = dtg * uu[0], DY = dtg * uu[1], DZ = dtg * uu[2];
+  CT dx1, dx2, dphi;
+  axi_move<GEOM, CT>(g, M, x2, sp, cp, DX, DY, DZ, dx1, dx2, dphi);
+  int m[3] = {0, 0, 0};
+  OffT<Real> qn1, qn2;
+  m[0] = PS::move(q[0], (double)dx1, qn1);
+  m[1] = PS::move(q[1], (double)dx2, qn2);
+  int inew1 = i[1] + m[1];
+  bool clamp = false;
+  if (inew1 < 0) {
+    inew1 = 0;
+    qn2 = (OffT<Real>)0;
+    clamp = true;
+  } else if (inew1 >= g.n[1]) {
+    inew1 = g.n[1] - 1;
+    qn2 = largest_offset<Real>();
+    clamp = true;
+  }
+  m[1] = inew1 - i[1];
+  // ---- reverse
+  Real dxb[3] = {0, 0, 0}, dx3b = 0;
+  {
+    const Real l1 = A.lam_d[0][p];
+    ab[0] += l1;
+    dxb[0] += l1;
+    if (!clamp) {
+      const Real l2 = A.lam_d[1][p];
+      ab[1] += l2;
+      dxb[1] += l2;
+    }
+  }
+  if (A.lamJ) {
+    const double za[3] = {PS::exact(q[0]), PS::exact(q[1]), 0.0};
+    const double zb[3] = {PS::exact(qn1) + (double)m[0], PS::exact(qn2) + (double)m[1], 0.0};
+    const bool bfix[3] = {false, clamp, false};
+    zigzag_rev<2, Real>(LJ, i, m, za, zb, (Real)A.sp.qdt[s] * A.p.w[p], (Real)dphi, bfix, ab, dxb,
+                        dx3b);
+  }
+  // phi_new = phi + dphi (wrapped)
+  const Real phinb = A.lam_phi[p];
+  CT phib = (CT)phinb;
+  const CT dphib = (CT)dx3b + (CT)phinb;
+  AxiMetricBar<CT> Mb{0, 0, 0, 0, 0, 0, 0};
+  CT x1b = 0, x2b = 0, spb = 0, cpb = 0;
+  CT DXb[3] = {0, 0, 0};
+  axi_move_rev<GEOM, CT>(g, M, x2, sp, cp, DX, DY, DZ, (CT)dxb[0], (CT)dxb[1], dphib, Mb, x2b, spb,
+                         cpb, DXb);
+  // DX = dt u / gamma
+  const CT uw = uu[0] * DXb[0] + uu[1] * DXb[1] + uu[2] * DXb[2];
+  Real unb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    unb[a] = A.lam_u[a][p] + (Real)(dtg * DXb[a] - (CT)A.dt * gi * gi * gi * uu[a] * uw);
+  Real ub[3], Eb[3], Bb[3];
+  boris_rev(k, R, unb, ub, Eb, Bb);
+  axi_to_cart_rev<CT, Real>(M, sp, cp, F, Eb, Bb, Fb, Mb, spb, cpb);
+  phib += spb * cp - cpb * sp;
+  axi_metric_rev<GEOM, CT>(g, M, x2, Mb, x1b, x2b);
+  ab[0] += (Real)x1b;
+  ab[1] += (Real)x2b;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.lam_u[a][p] = ub[a];
+  A.lam_phi[p] = (Real)phib;
 }
 
 // One particle per thread, BLOCK particles per block in XCD-aware order.  The
@@ -68,17 +351,17 @@ __device__ __forceinline__ void stage_box(const GridConst &g, const Real *__rest
 // fixed point in FP32 builds, scaled by the block's largest |dL/dF|) and
 // flushed with one global atomic per nonzero value; particles whose stencil
 // leaves the tile scatter with global atomics.
-// Waves per SIMD the register allocation must allow: the FP32 instances run
-// faster at 4 (a few spills) than uncapped at 3 (0.457 -> 0.41 ms per step on
-// the 64^3 workload); the FP64 ones stay uncapped.
-template <class Real>
+// Waves per SIMD the register allocation must allow: the FP32 Cartesian
+// instances run faster at 4 (a few spills) than uncapped at 3 (0.457 -> 0.41
+// ms per step on the 64^3 workload); the others stay uncapped.
+template <int GEOM, class Real>
 constexpr int adj_waves() {
-  return sizeof(Real) == 4 ? 4 : 1;
+  return (GEOM == 0 && sizeof(Real) == 4) ? 4 : 1;
 }
 
-template <int DIM, class Real>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(adj_waves<Real>(), 8)))
-void k_adjoint_cart(AdjArgs<Real> A) {
+template <int GEOM, int DIM, class Real>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(adj_waves<GEOM, Real>(), 8)))
+void k_adjoint(AdjArgs<Real> A) {
   using PS = Pos<Real>;
   using Acc = typename TileAcc<Real>::type;
   constexpr int TILE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Acc);
@@ -112,22 +395,25 @@ void k_adjoint_cart(AdjArgs<Real> A) {
   }
   block_minmax3(lo, hi, red);
   if (lo[0] > hi[0]) return;  // no live particle in the block (uniform)
-  int shift[3] = {0, 0, 0}, ib[3] = {i[0], i[1], i[2]};
-  bool any = false;
+  int ib[3] = {i[0], i[1], i[2]};
+  if (GEOM == 0) {
+    int shift[3] = {0, 0, 0};
+    bool any = false;
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    shift[d] = (hi[d] - lo[d] > (g.n[d] >> 1)) ? 1 : 0;
-    any = any || shift[d];
-    if (shift[d] && ib[d] < (g.n[d] >> 1)) ib[d] += g.n[d];
-  }
-  if (any) {  // a block straddling a periodic boundary: box of the unwrapped cells
-    __syncthreads();
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = live ? ib[d] : INT32_MAX;
-      hi[d] = live ? ib[d] : INT32_MIN;
+    for (int d = 0; d < DIM; ++d) {
+      shift[d] = (hi[d] - lo[d] > (g.n[d] >> 1)) ? 1 : 0;
+      any = any || shift[d];
+      if (shift[d] && ib[d] < (g.n[d] >> 1)) ib[d] += g.n[d];
     }
-    block_minmax3(lo, hi, red);
+    if (any) {  // a block straddling a periodic boundary: box of the unwrapped cells
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = live ? ib[d] : INT32_MAX;
+        hi[d] = live ? ib[d] : INT32_MIN;
+      }
+      block_minmax3(lo, hi, red);
+    }
   }
   int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1}, j0[3] = {0, 0, 0}, js[3] = {1, 1, 1};
   int T = 1, TJ = 1;
@@ -164,8 +450,8 @@ void k_adjoint_cart(AdjArgs<Real> A) {
     }
   }
   if (stage) {
-    stage_box<DIM, Real>(g, A.EB, 6, t0, ts, lds.f);
-    if (A.lamJ) stage_box<DIM, Real>(g, A.lamJ, 3, j0, js, lds.f + 6 * T);
+    stage_box<GEOM, DIM, Real>(g, A.EB, 6, t0, ts, lds.f);
+    if (A.lamJ) stage_box<GEOM, DIM, Real>(g, A.lamJ, 3, j0, js, lds.f + 6 * T);
     __syncthreads();
   }
   const int dsh[3] = {ib[0] - i[0], ib[1] - i[1], ib[2] - i[2]};  // unwrapped - stored
@@ -174,272 +460,96 @@ void k_adjoint_cart(AdjArgs<Real> A) {
   Stencil1<Real> st[3];
   float bmax = 0.0f;
   if (live) {
-  OffT<Real> q[3];
-  Real d[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    q[a] = A.p.offs[a][p];
-    d[a] = (Real)PS::weight(q[a]);
-  }
-  const Real u0[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
-  const Real w = A.p.w[p];
-  const Real k = (Real)A.sp.k[s];
-  const Real dtr = (Real)A.dt;
-
-  // ---------------- forward recompute (step 3: interpolation, keeping corners)
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], d[a]);
-  Real F[6];
-  FieldTile<Real> ft;
-  ft.F = lds.f;
-  ft.T = T;
-  ft.sy = ts[0];
-  ft.sz = ts[0] * ts[1];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    ft.o[a] = t0[a];
-    ft.ts[a] = ts[a];
-  }
-  if (stage)
-    interp6_tile<DIM, Real>(ft, dsh, st, F);
-  else
-    interp6<DIM, Real>(A.EB, g, st, F);
-  Real E[3], B[3], sc[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    sc[a] = (a < DIM) ? (Real)g.dx[a] : (Real)1;
-    E[a] = F[a] * sc[a];
-    B[a] = F[3 + a] * sc[a];
-  }
-  // step 5: Boris, keeping intermediates
-  Real um[3], t[3], s3[3], up[3], un[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) um[a] = u0[a] + k * E[a];
-  // same operations as the forward kernel, so the recomputed step is identical
-  const Real igm = rsqrt_r((Real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) t[a] = k * B[a] * igm;
-  const Real tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-  const Real sf = (Real)2 * rcp_r((Real)1 + tt);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) s3[a] = t[a] * sf;
-  up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
-  up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
-  up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-  un[0] = um[0] + (up[1] * s3[2] - up[2] * s3[1]) + k * E[0];
-  un[1] = um[1] + (up[2] * s3[0] - up[0] * s3[2]) + k * E[1];
-  un[2] = um[2] + (up[0] * s3[1] - up[1] * s3[0]) + k * E[2];
-  // steps 6-7: move
-  const Real ig = rsqrt_r((Real)1 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-  int m[3] = {0, 0, 0};
-  double za[3] = {0, 0, 0}, zb[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const Real dx = cart_disp(g, a, dtr, un[a], ig);  // as in the forward kernel
-    OffT<Real> qn;
-    m[a] = PS::move(q[a], (double)dx, qn);
-    za[a] = PS::exact(q[a]);
-    zb[a] = PS::exact(qn) + (double)m[a];
-  }
-
-  // ---------------- reverse
-  Real ab[3] = {0, 0, 0};   // adjoint of the old offsets
-  Real dxb[3] = {0, 0, 0};  // adjoint of the in-plane displacements
-  Real dx3b = 0;            // adjoint of the out-of-plane displacement (2D)
-  // adjoint of the new offsets passes to the old offset and the displacement
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const Real l = A.lam_d[a][p];
-    ab[a] += l;
-    dxb[a] += l;
-  }
-  // step 8 reversed: gather dL/dJ through the zig-zag segments
-  if (A.lamJ) {
-    const Real C = (Real)A.sp.qdt[s] * w;
-    Real Fs[2][3] = {{0, 0, 0}, {0, 0, 0}}, Ws[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    bool mid_free[3] = {false, false, false};
+    OffT<Real> q[3] = {(OffT<Real>)0, (OffT<Real>)0, (OffT<Real>)0};
+    Real d[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      const double lo = (double)(min(0, m[a]) + 1), hi = (double)max(0, m[a]);
-      const double mid = (za[a] + zb[a]) * 0.5;
-      const double xr = fmin(lo, fmax(hi, mid));
-      mid_free[a] = (mid >= hi) && (mid <= lo);
-      Fs[0][a] = (Real)(xr - za[a]);
-      Fs[1][a] = (Real)(zb[a] - xr);
-      Ws[0][a] = (Real)((za[a] + xr) * 0.5);
-      Ws[1][a] = (Real)((xr + zb[a]) * 0.5 - (double)m[a]);
+      q[a] = A.p.offs[a][p];
+      d[a] = (Real)PS::weight(q[a]);
+      st[a] = stencil1(i[a], d[a]);
     }
-    const Real dx3 = (DIM == 2) ? dtr * un[2] * ig : (Real)0;
-    Real Fb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Wb[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    // dL/dJ from the LDS copy (box frame) or from global memory
-    const Real *L = stage ? lds.f + 6 * T : A.lamJ;
-    const int cs = stage ? TJ : (int)g.npts;
-    const int sy = stage ? js[0] : g.np[0];
-    const int sz = stage ? js[0] * js[1] : g.np[0] * g.np[1];
+    // ---------------- forward recompute of step 3 (interpolation)
+    FieldTile<Real> ft;
+    ft.F = lds.f;
+    ft.T = T;
+    ft.sy = ts[0];
+    ft.sz = ts[0] * ts[1];
 #pragma unroll
-    for (int sg = 0; sg < 2; ++sg) {
-      const int I = i[0] + (sg ? m[0] : 0), Jc = i[1] + (sg ? m[1] : 0);
-      const int K = (DIM == 3) ? i[2] + (sg ? m[2] : 0) : 0;
-      const int base = stage ? (I + dsh[0] - j0[0]) + sy * (Jc + dsh[1] - j0[1]) +
-                                   ((DIM == 3) ? sz * (K + dsh[2] - j0[2]) : 0)
-                             : pad_index(g, I, Jc, K, DIM);
-      const Real Fx = Fs[sg][0], Fy = Fs[sg][1], Wx = Ws[sg][0], Wy = Ws[sg][1];
-      if (DIM == 2) {
-        const Real l10 = L[base], l11 = L[base + sy];
-        const Real l20 = L[cs + base], l21 = L[cs + base + 1];
-        Fb[sg][0] += C * (l10 * ((Real)1 - Wy) + l11 * Wy);
-        Wb[sg][1] += C * Fx * (l11 - l10);
-        Fb[sg][1] += C * (l20 * ((Real)1 - Wx) + l21 * Wx);
-        Wb[sg][0] += C * Fy * (l21 - l20);
-        const Real *L3 = L + 2 * cs + base;
-        const Real a00 = L3[0], a10 = L3[1], a01 = L3[sy], a11 = L3[sy + 1];
-        const Real h = C * dx3 * (Real)0.5;
-        const Real cxy = Fx * Fy * (Real)(1.0 / 12.0);
-        const Real val = a00 * (((Real)1 - Wx) * ((Real)1 - Wy) + cxy) +
-                         a10 * (Wx * ((Real)1 - Wy) - cxy) + a01 * (((Real)1 - Wx) * Wy - cxy) +
-                         a11 * (Wx * Wy + cxy);
-        dx3b += C * (Real)0.5 * val;
-        Wb[sg][0] += h * (-a00 * ((Real)1 - Wy) + a10 * ((Real)1 - Wy) - a01 * Wy + a11 * Wy);
-        Wb[sg][1] += h * (-a00 * ((Real)1 - Wx) - a10 * Wx + a01 * ((Real)1 - Wx) + a11 * Wx);
-        const Real csum = (a00 - a10 - a01 + a11) * h * (Real)(1.0 / 12.0);
-        Fb[sg][0] += csum * Fy;
-        Fb[sg][1] += csum * Fx;
-      } else {
-        const Real Fz = Fs[sg][2], Wz = Ws[sg][2];
-        // component c with transverse dims (a, b): value = C F_c (w_a w_b + sgn F_a F_b / 12)
-#pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-          const int da = (comp == 0) ? 1 : 0;
-          const int db = (comp == 2) ? 1 : 2;
-          const int sa = (da == 0) ? 1 : sy;
-          const int sb = (db == 1) ? sy : sz;
-          const Real *Lc = L + comp * cs + base;
-          const Real l00 = Lc[0], l10 = Lc[sa], l01 = Lc[sb], l11 = Lc[sa + sb];
-          const Real Fc = (comp == 0) ? Fx : (comp == 1 ? Fy : Fz);
-          const Real Wa = Ws[sg][da], Wbb = Ws[sg][db];
-          const Real Fa = Fs[sg][da], Fbt = Fs[sg][db];
-          const Real ga = (Real)1 - Wa, gb = (Real)1 - Wbb;
-          const Real cab = Fa * Fbt * (Real)(1.0 / 12.0);
-          const Real sgn = l00 - l10 - l01 + l11;
-          const Real val = l00 * (ga * gb + cab) + l10 * (Wa * gb - cab) + l01 * (ga * Wbb - cab) +
-                           l11 * (Wa * Wbb + cab);
-          Fb[sg][comp] += C * val;
-          Wb[sg][da] += C * Fc * (-l00 * gb + l10 * gb - l01 * Wbb + l11 * Wbb);
-          Wb[sg][db] += C * Fc * (-l00 * ga - l10 * Wa + l01 * ga + l11 * Wa);
-          Fb[sg][da] += C * Fc * sgn * Fbt * (Real)(1.0 / 12.0);
-          Fb[sg][db] += C * Fc * sgn * Fa * (Real)(1.0 / 12.0);
-        }
-        (void)Fz;
-        (void)Wz;
-      }
+    for (int a = 0; a < 3; ++a) {
+      ft.o[a] = t0[a];
+      ft.ts[a] = ts[a];
     }
-    // relay: F1 = xr - a, F2 = b - xr, W1 = (a + xr)/2, W2 = (xr + b)/2 - m
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      Real xrb = Fb[0][a] - Fb[1][a] + (Real)0.5 * (Wb[0][a] + Wb[1][a]);
-      Real abar = -Fb[0][a] + (Real)0.5 * Wb[0][a];
-      Real bbar = Fb[1][a] + (Real)0.5 * Wb[1][a];
-      if (mid_free[a]) {  // xr = (a + b)/2
-        abar += (Real)0.5 * xrb;
-        bbar += (Real)0.5 * xrb;
-      }
-      // b = a + dx
-      ab[a] += abar + bbar;
-      dxb[a] += bbar;
-    }
-  }
-  // steps 6-7 reversed: dx_a = dt u_a / (gamma Delta_a); 2D also dx3 = dt u_z / gamma
-  Real wv[3] = {0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) wv[a] = dxb[a] * dtr / (Real)g.dx[a];
-  if (DIM == 2) wv[2] = dx3b * dtr;
-  const Real uw = un[0] * wv[0] + un[1] * wv[1] + un[2] * wv[2];
-  Real unb[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) unb[a] = A.lam_u[a][p] + wv[a] * ig - un[a] * uw * ig * ig * ig;
-  // step 5 reversed (Boris)
-  Real Eb[3], Bb[3], umb[3], upb[3], sb[3], tb[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    Eb[a] = k * unb[a];  // u+ = u+' + k E
-    umb[a] = unb[a];     // u+' = um + up x s
-  }
-  // up x s: upb += s x unb, sb = unb x up
-  upb[0] = s3[1] * unb[2] - s3[2] * unb[1];
-  upb[1] = s3[2] * unb[0] - s3[0] * unb[2];
-  upb[2] = s3[0] * unb[1] - s3[1] * unb[0];
-  sb[0] = unb[1] * up[2] - unb[2] * up[1];
-  sb[1] = unb[2] * up[0] - unb[0] * up[2];
-  sb[2] = unb[0] * up[1] - unb[1] * up[0];
-  // up = um + um x t: umb += upb + t x upb, tb = upb x um
-#pragma unroll
-  for (int a = 0; a < 3; ++a) umb[a] += upb[a];
-  umb[0] += t[1] * upb[2] - t[2] * upb[1];
-  umb[1] += t[2] * upb[0] - t[0] * upb[2];
-  umb[2] += t[0] * upb[1] - t[1] * upb[0];
-  tb[0] = upb[1] * um[2] - upb[2] * um[1];
-  tb[1] = upb[2] * um[0] - upb[0] * um[2];
-  tb[2] = upb[0] * um[1] - upb[1] * um[0];
-  // s = t sf, sf = 2 / (1 + t.t)
-  const Real ts = t[0] * sb[0] + t[1] * sb[1] + t[2] * sb[2];
-  const Real c4 = (Real)4 / (((Real)1 + tt) * ((Real)1 + tt));
-#pragma unroll
-  for (int a = 0; a < 3; ++a) tb[a] += sf * sb[a] - c4 * t[a] * ts;
-  // t = k B / gm
-  Real gmb = 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    Bb[a] = k * igm * tb[a];
-    gmb -= t[a] * tb[a] * igm;
-  }
-  // gm = sqrt(1 + um.um); um = u + k E
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    umb[a] += gmb * um[a] * igm;
-    Eb[a] += k * umb[a];
-  }
-  // tetrad reversed; the offset derivative of the interpolation
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    Fbar[a] = Eb[a] * sc[a];
-    Fbar[3 + a] = Bb[a] * sc[a];
-  }
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
-    const int bx = sx ? st[0].bh : st[0].b0;
-    const int by = sy2 ? st[1].bh : st[1].b0;
-    const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
-    const Real fx = sx ? st[0].fh : st[0].f0;
-    const Real fy = sy2 ? st[1].fh : st[1].f0;
-    const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
-    Real cv[8];
+    Real F[6];
     if (stage)
-      corners<DIM, Real>(lds.f + c * T, (bx + dsh[0] - t0[0]) + ft.sy * (by + dsh[1] - t0[1]) +
-                                            ((DIM == 3) ? ft.sz * (bz + dsh[2] - t0[2]) : 0),
-                         ft.sy, ft.sz, cv);
+      interp6_tile<DIM, Real>(ft, dsh, st, F);
     else
-      corners<DIM, Real>(A.EB + c * (int)g.npts, pad_index(g, bx, by, bz, DIM), g.np[0],
-                         g.np[0] * g.np[1], cv);
-    const Real gx = (Real)1 - fx, gy = (Real)1 - fy, gz = (Real)1 - fz;
-    const Real fb = Fbar[c];
-    bmax = fmaxf(bmax, fabsf((float)fb));
-    if (DIM == 2) {
-      ab[0] += fb * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]));
-      ab[1] += fb * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]));
+      interp6<DIM, Real>(A.EB, g, st, F);
+    // dL/dJ from the LDS copy (box frame) or from global memory
+    BoxView<Real> LJ;
+    if (stage) {
+      LJ.L = lds.f + 6 * T;
+      LJ.cs = TJ;
+      LJ.sy = js[0];
+      LJ.sz = js[0] * js[1];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) LJ.o[a] = j0[a] - dsh[a];
     } else {
-      ab[0] += fb * (gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
-                     fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6])));
-      ab[1] += fb * (gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
-                     fz * (gx * (cv[6] - cv[4]) + fx * (cv[7] - cv[5])));
-      ab[2] += fb * (gy * (gx * (cv[4] - cv[0]) + fx * (cv[5] - cv[1])) +
-                     fy * (gx * (cv[6] - cv[2]) + fx * (cv[7] - cv[3])));
+      LJ.L = A.lamJ;
+      LJ.cs = (int)g.npts;
+      LJ.sy = g.np[0];
+      LJ.sz = g.np[0] * g.np[1];
+      LJ.o[0] = -NG;
+      LJ.o[1] = -NG;
+      LJ.o[2] = (DIM == 3) ? -NG : 0;
     }
-  }
+    Real ab[3] = {0, 0, 0};  // adjoint of the old offsets
+    if constexpr (GEOM == 0) {
+      cart_particle_rev<DIM, Real>(A, s, p, i, q, F, LJ, Fbar, ab);
+    } else {
+      const bool near = (i[0] < g.fp64_cells) || (i[1] < g.fp64_cells) ||
+                        (i[1] >= g.n[1] - g.fp64_cells);
+      if (sizeof(Real) == 8 || near)
+        axi_particle_rev<GEOM, double, Real>(A, s, p, i, q, PS::exact(q[0]), PS::exact(q[1]), F,
+                                             LJ, Fbar, ab);
+      else
+        axi_particle_rev<GEOM, float, Real>(A, s, p, i, q, d[0], d[1], F, LJ, Fbar, ab);
+    }
+    // the offset derivative of the interpolation weights
 #pragma unroll
-  for (int a = 0; a < 3; ++a) A.lam_u[a][p] = umb[a];
+    for (int c = 0; c < 6; ++c) {
+      const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
+      const int bx = sx ? st[0].bh : st[0].b0;
+      const int by = sy2 ? st[1].bh : st[1].b0;
+      const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
+      const Real fx = sx ? st[0].fh : st[0].f0;
+      const Real fy = sy2 ? st[1].fh : st[1].f0;
+      const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
+      Real cv[8];
+      if (stage)
+        corners<DIM, Real>(lds.f + c * T, (bx + dsh[0] - t0[0]) + ft.sy * (by + dsh[1] - t0[1]) +
+                                              ((DIM == 3) ? ft.sz * (bz + dsh[2] - t0[2]) : 0),
+                           ft.sy, ft.sz, cv);
+      else
+        corners<DIM, Real>(A.EB + c * (int)g.npts, pad_index(g, bx, by, bz, DIM), g.np[0],
+                           g.np[0] * g.np[1], cv);
+      const Real gx = (Real)1 - fx, gy = (Real)1 - fy;
+      const Real fb = Fbar[c];
+      bmax = fmaxf(bmax, fabsf((float)fb));
+      if (DIM == 2) {
+        ab[0] += fb * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]));
+        ab[1] += fb * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]));
+      } else {
+        const Real gz = (Real)1 - fz;
+        ab[0] += fb * (gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
+                       fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6])));
+        ab[1] += fb * (gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
+                       fz * (gx * (cv[6] - cv[4]) + fx * (cv[7] - cv[5])));
+        ab[2] += fb * (gy * (gx * (cv[4] - cv[0]) + fx * (cv[5] - cv[1])) +
+                       fy * (gx * (cv[6] - cv[2]) + fx * (cv[7] - cv[3])));
+      }
+    }
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
+    for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
   }  // live
 
   // ---------------- scatter of dL/dF into the tile (or global memory)
@@ -525,18 +635,30 @@ void k_adjoint_cart(AdjArgs<Real> A) {
         });
     return;
   }
+  // (curvilinear: tile points outside the padded lattice hold nothing)
   tile_for_each<8, Acc>(
       6, DIM == 3 ? 2 : 1, ts[0], ts[1], ts[2],
       [&](int ix, int iy) {
-        const int gx = wrap_periodic(t0[0] + ix, g.n[0]);
-        const int gy = (DIM == 3) ? wrap_periodic(t0[1] + iy, g.n[1]) : 0;
-        return PlanePt{(gx + NG) + ((DIM == 3) ? np0 * (gy + NG) : 0), true};
+        int gx = t0[0] + ix, gy = (DIM == 3) ? t0[1] + iy : 0;
+        bool ok = true;
+        if (GEOM == 0) {
+          gx = wrap_periodic(gx, g.n[0]);
+          if (DIM == 3) gy = wrap_periodic(gy, g.n[1]);
+        } else {
+          ok = gx >= -NG && gx < g.n[0] + NG;
+        }
+        return PlanePt{(gx + NG) + ((DIM == 3) ? np0 * (gy + NG) : 0), ok};
       },
       [&](const PlanePt &, int x, int, int) { return tile[x]; },
       [&](const PlanePt &pp, int, int comp, int w, Acc acc) {
         if (acc == (Acc)0) return;
+        int gw = t0[WA] + w;
+        if (GEOM == 0) {
+          gw = wrap_periodic(gw, g.n[WA]);
+        } else if (!pp.ok || gw < -NG || gw >= g.n[WA] + NG) {
+          return;
+        }
         const Real v = (Real)ldexp((double)acc, -esc);
-        const int gw = wrap_periodic(t0[WA] + w, g.n[WA]);
         atomic_add_r(A.dEB + comp * npts + pp.off + wstride * (gw + NG), v);
       });
 }
@@ -545,12 +667,18 @@ template <class Real>
 hipError_t launch_adjoint_step(const AdjArgs<Real> &a, hipStream_t s) {
   const int64_t nblk = a.sp.blk0[a.sp.nspec];
   if (nblk == 0) return hipSuccess;
-  if (a.g.geom != 0) return hipErrorNotSupported;
+  if (a.g.geom != 0 && !a.lam_phi) return hipErrorInvalidValue;
   dim3 grid((unsigned)nblk), block(BLOCK);
-  if (a.g.dim == 2)
-    hipLaunchKernelGGL((k_adjoint_cart<2, Real>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_adjoint_cart<3, Real>), grid, block, 0, s, a);
+  if (a.g.geom == 0) {
+    if (a.g.dim == 2)
+      hipLaunchKernelGGL((k_adjoint<0, 2, Real>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adjoint<0, 3, Real>), grid, block, 0, s, a);
+  } else if (a.g.geom == 1) {
+    hipLaunchKernelGGL((k_adjoint<1, 2, Real>), grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_adjoint<2, 2, Real>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -152,7 +152,7 @@ __device__ __forceinline__ void particle_fields(const StepArgs<Real> &A, const F
     interp6<DIM, Real>(A.EB, A.g, st, F);
 }
 
-template <int DIM, class Real, bool CHK>
+template <int DIM, class Real, bool CHK, bool PUSHERS>
 __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
                                              const int shift[3], int s, int32_t c,
                                              OffT<Real> q[3], Real u[3], int &mp, Real &dx3,
@@ -173,7 +173,10 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const Fiel
     E[a] = F[a] * sc;
     B[a] = F[3 + a] * sc;
   }
-  boris((Real)A.sp.k[s], E, B, u);
+  if (PUSHERS)
+    push_momentum<Real>(A.sp, s, (Real)A.sp.k[s], A.dt, E, B, u);
+  else
+    boris((Real)A.sp.k[s], E, B, u);
   // move (steps 6-7): offsets advance by dt u / (gamma Delta)
   const Real gi = rsqrt_r((Real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const Real dtr = (Real)A.dt;
@@ -197,54 +200,7 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const Fiel
   return cell_encode(g, inew);
 }
 
-// Axisymmetric: tetrad (F^i_hat = sqrt(h_ii) F^i at x_p) and rotation of
-// (r, theta, phi)_hat into (x, y, z)_hat (Sec. 2.3 step 4), Boris in the
-// global basis, offset-relative move.  Metric and move run in CT (FP64 near
-// the axis and r_min when Real is float).
-template <int GEOM, class CT, class Real, class D>
-__device__ __forceinline__ void axi_particle(const GridConst &g, Real k, double dt, int i1, int i2,
-                                             D d1, D d2, Real phi, const Real F[6], Real u[3],
-                                             CT &dx1, CT &dx2, CT &dphi) {
-  const CT x1 = (CT)i1 + (CT)d1;
-  const CT x2 = (CT)i2 + (CT)d2;
-  const AxiMetric<CT> M = axi_metric<GEOM, CT>(g, x1, x2);
-  CT sp, cp;
-  sincos_r((CT)phi, &sp, &cp);
-  Real E[3], B[3];
-  {
-    const CT h[3] = {M.h1, M.h2, M.h3};
-    CT Fh[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) Fh[c] = (CT)F[c] * h[c % 3];
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const CT a = Fh[3 * f], b = Fh[3 * f + 1], cc = Fh[3 * f + 2];
-      const CT ax = a * M.st + b * M.ct;  // cylindrical radial component
-      Real *out = f ? B : E;
-      out[0] = (Real)(ax * cp - cc * sp);
-      out[1] = (Real)(ax * sp + cc * cp);
-      out[2] = (Real)(a * M.ct - b * M.st);
-    }
-  }
-  boris(k, E, B, u);
-  const CT uu0 = (CT)u[0], uu1 = (CT)u[1], uu2 = (CT)u[2];
-  const CT gi = rsqrt_r((CT)1 + uu0 * uu0 + uu1 * uu1 + uu2 * uu2);
-  const CT dtg = (CT)dt * gi;
-  axi_move<GEOM, CT>(g, M, x2, sp, cp, dtg * uu0, dtg * uu1, dtg * uu2, dx1, dx2, dphi);
-}
-
-template <class Real, class CT>
-__device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
-  CT pn = (CT)phi + dphi;
-  const CT twopi = (CT)(2.0 * kPI);
-  if (pn < (CT)0) pn += twopi;
-  if (pn >= twopi) pn -= twopi;
-  Real pr = (Real)pn;
-  if (pr >= (Real)(2.0 * kPI)) pr = (Real)0;
-  return pr;
-}
-
-template <int GEOM, class Real, bool CHK>
+template <int GEOM, class Real, bool CHK, bool PUSHERS>
 __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, const FieldTile<Real> &ft,
                                             int s, int32_t c, OffT<Real> q[3], Real u[3],
                                             Real &phi, int &mp, Real &dx3, float &span) {
@@ -259,20 +215,21 @@ __device__ __forceinline__ int32_t axi_push(const StepArgs<Real> &A, const Field
   Real F[6];
   const int noshift[3] = {0, 0, 0};
   particle_fields<2, Real, CHK>(A, ft, i, noshift, st, F);
-  const Real k = (Real)A.sp.k[s];
   double dx1, dx2;
   Real phinew;
   const bool near = (i[0] < g.fp64_cells) || (i[1] < g.fp64_cells) ||
                     (i[1] >= g.n[1] - g.fp64_cells);
   if (sizeof(Real) == 8 || near) {
     double dphi;
-    axi_particle<GEOM, double, Real>(g, k, A.dt, i[0], i[1], PS::exact(q[0]), PS::exact(q[1]),
+    axi_particle<GEOM, double, Real, double, PUSHERS>(g, A.sp, s, A.dt, i[0], i[1],
+                                                      PS::exact(q[0]), PS::exact(q[1]),
                                      phi, F, u, dx1, dx2, dphi);
     phinew = next_phi<Real, double>(phi, dphi);
     dx3 = (Real)dphi;
   } else {
     float f1, f2, dphi;
-    axi_particle<GEOM, float, Real>(g, k, A.dt, i[0], i[1], d1, d2, phi, F, u, f1, f2, dphi);
+    axi_particle<GEOM, float, Real, Real, PUSHERS>(g, A.sp, s, A.dt, i[0], i[1], d1, d2, phi, F,
+                                                   u, f1, f2, dphi);
     dx1 = f1;
     dx2 = f2;
     phinew = next_phi<Real, float>(phi, dphi);
@@ -360,7 +317,9 @@ constexpr int push_waves() {
   return (GEOM == 0 && sizeof(Real) == 4) ? 4 : 1;
 }
 
-template <int GEOM, int DIM, class Real>
+// PUSHERS: some species uses another pusher than Boris (a separate instance,
+// so the plain Boris kernel carries no code for them).
+template <int GEOM, int DIM, class Real, bool PUSHERS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(push_waves<GEOM, DIM, Real>(), 8)))
 void k_push(StepArgs<Real> A) {
   using Acc = typename TileAcc<Real>::type;
@@ -620,10 +579,11 @@ void k_push(StepArgs<Real> A) {
       float span = 0.0f;
       Real dx3;
       if (GEOM == 0) {
-        cl[r] = cart_push<DIM, Real, CHK>(A, ft, shift, s, cl[r], q, u, mp[r], dx3, span);
+        cl[r] = cart_push<DIM, Real, CHK, PUSHERS>(A, ft, shift, s, cl[r], q, u, mp[r], dx3,
+                                                   span);
       } else {
         Real p = ph[r];
-        cl[r] = axi_push<GEOM, Real, CHK>(A, ft, s, cl[r], q, u, p, mp[r], dx3, span);
+        cl[r] = axi_push<GEOM, Real, CHK, PUSHERS>(A, ft, s, cl[r], q, u, p, mp[r], dx3, span);
         ph[r] = p;
       }
       d3[r] = dx3;
@@ -738,22 +698,30 @@ void k_push(StepArgs<Real> A) {
   }
 }
 
+template <class Real, bool PUSHERS>
+hipError_t launch_push_instance(const StepArgs<Real> &a, dim3 grid, dim3 block, hipStream_t s) {
+  if (a.g.geom == 0) {
+    if (a.g.dim == 2)
+      hipLaunchKernelGGL((k_push<0, 2, Real, PUSHERS>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_push<0, 3, Real, PUSHERS>), grid, block, 0, s, a);
+  } else if (a.g.geom == 1) {
+    hipLaunchKernelGGL((k_push<1, 2, Real, PUSHERS>), grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_push<2, 2, Real, PUSHERS>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <class Real>
 hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s) {
   const int64_t nblk = a.sp.blk0[a.sp.nspec];
   if (nblk == 0) return hipSuccess;
   dim3 grid((unsigned)nblk), block(BLOCK);
-  if (a.g.geom == 0) {
-    if (a.g.dim == 2)
-      hipLaunchKernelGGL((k_push<0, 2, Real>), grid, block, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_push<0, 3, Real>), grid, block, 0, s, a);
-  } else if (a.g.geom == 1) {
-    hipLaunchKernelGGL((k_push<1, 2, Real>), grid, block, 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_push<2, 2, Real>), grid, block, 0, s, a);
-  }
-  return hipGetLastError();
+  bool pushers = false;
+  for (int t = 0; t < a.sp.nspec; ++t) pushers = pushers || a.sp.pusher[t] != 0;
+  return pushers ? launch_push_instance<Real, true>(a, grid, block, s)
+                 : launch_push_instance<Real, false>(a, grid, block, s);
 }
 
 template hipError_t launch_push_deposit<float>(const StepArgs<float> &, hipStream_t);

@@ -35,6 +35,8 @@ struct pic_ctx {
   size_t eb = 4;  // element bytes
   int nspec = 0;
   double q[MAXSP]{}, m[MAXSP]{};
+  int pusher[MAXSP]{};                       // pic_pusher per species
+  double gca_e_ovr[MAXSP]{}, gca_larmor[MAXSP]{};
   uint64_t cap[MAXSP]{}, off[MAXSP]{}, cnt[MAXSP]{};
   uint64_t capacity = 0;  // elements per particle array
   // particle set layout (byte offsets)
@@ -150,6 +152,9 @@ SpeciesTable species_table(const pic_ctx *c, double dt, int64_t per_block) {
     t.blk0[s + 1] = t.blk0[s] + (t.n[s] + per_block - 1) / per_block;
     t.k[s] = c->q[s] * dt / (2.0 * c->m[s] * c->d.rho0);
     t.qdt[s] = c->q[s] / dt;
+    t.pusher[s] = c->pusher[s];
+    t.gca_e_ovr[s] = c->gca_e_ovr[s];
+    t.gca_larmor[s] = c->gca_larmor[s];
   }
   for (int s = c->nspec; s < MAXSP; ++s) t.blk0[s + 1] = t.blk0[c->nspec];
   return t;
@@ -428,7 +433,6 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
     if (e == hipSuccess) e = launch_fill_ghosts<Real>(g, lJ, 3, c->stream);
   }
   if (e != hipSuccess) return hipchk(c, e, "backward setup");
-  const PSet<Real> act = pset_of<Real>(c, c->active);
   AdjArgs<Real> A{};
   A.g = g;
   A.sp = species_table(c, dt, BLOCK);
@@ -439,7 +443,8 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
     A.lam_u[a] = lu[a];
     A.lam_d[a] = ld[a];
   }
-  A.lam_phi = nullptr;
+  // axisymmetric grids: the third row of the offset adjoints carries dL/dphi
+  A.lam_phi = g.geom != 0 ? ld[2] : nullptr;
   const int64_t saved_step = c->step;
   const bool has_phi = c->o_phi != NONE;
   for (int64_t j = (int64_t)L.nck - 1; j >= 0; --j) {
@@ -477,7 +482,8 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
       if (r >= 0) {  // the adjoints follow their particles back to the order before the sort
         const int32_t *pm = reinterpret_cast<const int32_t *>(ws + L.perm0 + r * L.perm_bytes);
         Real *arr[6] = {lu[0], lu[1], lu[2], ld[0], ld[1], ld[2]};
-        for (int k = 0; k < 3 + g.dim && e == hipSuccess; ++k) {
+        const int nadj = g.geom != 0 ? 6 : 3 + g.dim;
+        for (int k = 0; k < nadj && e == hipSuccess; ++k) {
           for (int sp = 0; sp < c->nspec && e == hipSuccess; ++sp)
             e = launch_scatter_back<Real>(arr[k], tmp, (int64_t)c->off[sp], (int64_t)c->cnt[sp],
                                           pm + c->off[sp], c->stream);
@@ -546,7 +552,7 @@ pic_status adjoint_one(pic_ctx *c, double dt, const void *lamJ, const pic_adjoin
     A.lam_u[a] = static_cast<Real *>(io->lam_u) + a * cap;
     A.lam_d[a] = static_cast<Real *>(io->lam_offs) + a * cap;
   }
-  A.lam_phi = nullptr;
+  A.lam_phi = g.geom != 0 ? A.lam_d[2] : nullptr;
   A.lamJ = nullptr;
   hipError_t e = hipSuccess;
   if (lamJ) {  // a deposit into a periodic ghost ends up in its image: gather from there
@@ -772,6 +778,32 @@ pic_status pic_species_add(pic_ctx *c, double charge, double mass, uint64_t capa
   c->off[s] = start;
   c->cnt[s] = 0;
   *species_id = s;
+  return PIC_OK;
+}
+
+pic_status pic_species_set_pusher(pic_ctx *c, int32_t species, int32_t pusher, double e_ovr,
+                                  double larmor_max) {
+  if (!c) return PIC_E_ARG;
+  if (species < 0 || species >= c->nspec) return fail(c, PIC_E_ARG, "no species %d", species);
+  if (pusher < 0 || pusher > (PIC_PUSH_VAY | PIC_PUSH_GCA))
+    return fail(c, PIC_E_ARG, "unknown pusher %d", pusher);
+  if (pusher & PIC_PUSH_GCA) {
+    if (!(e_ovr > 0.0 && e_ovr < 1.0))
+      return fail(c, PIC_E_ARG, "guiding-centre hybrid: e_ovr %g outside (0, 1)", e_ovr);
+    if (!(larmor_max > 0.0) || !isfin(larmor_max))
+      return fail(c, PIC_E_ARG, "guiding-centre hybrid: bad critical gyroradius %g", larmor_max);
+  }
+  c->pusher[species] = pusher;
+  c->gca_e_ovr[species] = (pusher & PIC_PUSH_GCA) ? e_ovr : 0.0;
+  c->gca_larmor[species] = (pusher & PIC_PUSH_GCA) ? larmor_max : 0.0;
+  return PIC_OK;
+}
+
+// the hand-written reverse step differentiates the Boris push
+static pic_status adjoint_pushers_ok(pic_ctx *c) {
+  for (int s = 0; s < c->nspec; ++s)
+    if (c->pusher[s] != PIC_PUSH_BORIS)
+      return fail(c, PIC_E_UNSUPPORTED, "adjoint: species %d does not use the Boris pusher", s);
   return PIC_OK;
 }
 
@@ -1121,8 +1153,8 @@ pic_status pic_adjoint_workspace(const pic_ctx *c, int32_t K, int32_t m, uint64_
 
 pic_status pic_forward_checkpointed(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws) {
   if (!c || !ws || K < 1 || m < 1) return PIC_E_ARG;
+  if (adjoint_pushers_ok(c) != PIC_OK) return PIC_E_UNSUPPORTED;
   if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "forward before bind/fields_set");
-  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (!(dt > 0) || dt > c->dx_min) return fail(c, PIC_E_ARG, "bad dt");
   const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;
@@ -1133,8 +1165,8 @@ pic_status pic_forward_checkpointed(pic_ctx *c, double dt, int32_t K, int32_t m,
 pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, const void *lamJ,
                         const void *lam_u, void *dEB, void *du0) {
   if (!c || !ws || !dEB || !du0 || K < 1 || m < 1) return PIC_E_ARG;
+  if (adjoint_pushers_ok(c) != PIC_OK) return PIC_E_UNSUPPORTED;
   if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "backward before bind/fields_set");
-  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (c->ckpt_K != K || c->ckpt_m != m)
     return fail(c, PIC_E_STATE, "backward(K=%d, m=%d) without a matching forward_checkpointed", K, m);
   if (dt != c->ckpt_dt)
@@ -1196,8 +1228,8 @@ pic_status pic_checkpoint_load(pic_ctx *c, const void *slot) {
 pic_status pic_adjoint_step(pic_ctx *c, double dt, const void *lamJ, const pic_adjoint_buffers *io) {
   if (!c || !io || !io->lam_u || !io->lam_offs || !io->dEB || (lamJ && !io->lamJ_work))
     return PIC_E_ARG;
+  if (adjoint_pushers_ok(c) != PIC_OK) return PIC_E_UNSUPPORTED;
   if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "adjoint_step before bind/fields_set");
-  if (c->g.geom != 0) return fail(c, PIC_E_UNSUPPORTED, "adjoint: Cartesian grids only");
   if (!(dt > 0) || dt > c->dx_min) return fail(c, PIC_E_ARG, "bad dt");
   const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;

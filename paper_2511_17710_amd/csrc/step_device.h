@@ -168,12 +168,20 @@ __device__ __forceinline__ void interp6_tile(const FieldTile<Real> &t, const int
 // ---------------------------------------------------------------- step 5: Boris
 // Relativistic Boris push (Boris 1970) of eq. curvspace-equations-of-motion,
 // k = q dt / (2 m rho0): half electric kick, magnetic rotation, half kick.
+// The intermediates, for the reverse sweep.
 template <class Real>
-__device__ __forceinline__ void boris(Real k, const Real E[3], const Real B[3], Real u[3]) {
+struct BorisRec {
+  Real um[3], igm, t[3], tt, sf, s[3], up[3];
+};
+
+template <class Real>
+__device__ __forceinline__ void boris_rec(Real k, const Real E[3], const Real B[3], Real u[3],
+                                          BorisRec<Real> &R) {
   Real um0 = u[0] + k * E[0], um1 = u[1] + k * E[1], um2 = u[2] + k * E[2];
   Real ig = rsqrt_r((Real)1 + um0 * um0 + um1 * um1 + um2 * um2);
   Real t0 = k * B[0] * ig, t1 = k * B[1] * ig, t2 = k * B[2] * ig;
-  Real sf = (Real)2 * rcp_r((Real)1 + t0 * t0 + t1 * t1 + t2 * t2);
+  Real tt = t0 * t0 + t1 * t1 + t2 * t2;
+  Real sf = (Real)2 * rcp_r((Real)1 + tt);
   Real s0 = t0 * sf, s1 = t1 * sf, s2 = t2 * sf;
   Real up0 = um0 + (um1 * t2 - um2 * t1);
   Real up1 = um1 + (um2 * t0 - um0 * t2);
@@ -181,6 +189,142 @@ __device__ __forceinline__ void boris(Real k, const Real E[3], const Real B[3], 
   u[0] = um0 + (up1 * s2 - up2 * s1) + k * E[0];
   u[1] = um1 + (up2 * s0 - up0 * s2) + k * E[1];
   u[2] = um2 + (up0 * s1 - up1 * s0) + k * E[2];
+  R.um[0] = um0; R.um[1] = um1; R.um[2] = um2;
+  R.igm = ig;
+  R.t[0] = t0; R.t[1] = t1; R.t[2] = t2;
+  R.tt = tt;
+  R.sf = sf;
+  R.s[0] = s0; R.s[1] = s1; R.s[2] = s2;
+  R.up[0] = up0; R.up[1] = up1; R.up[2] = up2;
+}
+
+template <class Real>
+__device__ __forceinline__ void boris(Real k, const Real E[3], const Real B[3], Real u[3]) {
+  BorisRec<Real> R;
+  boris_rec(k, E, B, u, R);
+}
+
+// Vay (2008) pusher: u_new = u + (q dt/m)(E + vbar x B), vbar the mean of the
+// velocities before and after the step, with the new Lorentz factor from the
+// closed-form root of that implicit relation; (q dt/m) E = 2kE and
+// (q dt/m)(v/2) x B = k v x B in code units.  It keeps the relativistic
+// E x B drift exactly, which Boris's rotation does not.
+template <class Real>
+__device__ __forceinline__ void vay(Real k, const Real E[3], const Real B[3], Real u[3]) {
+  const Real ig0 = rsqrt_r((Real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  const Real v0 = u[0] * ig0, v1 = u[1] * ig0, v2 = u[2] * ig0;
+  const Real w0 = u[0] + (Real)2 * k * E[0] + k * (v1 * B[2] - v2 * B[1]);
+  const Real w1 = u[1] + (Real)2 * k * E[1] + k * (v2 * B[0] - v0 * B[2]);
+  const Real w2 = u[2] + (Real)2 * k * E[2] + k * (v0 * B[1] - v1 * B[0]);
+  const Real t0 = k * B[0], t1 = k * B[1], t2 = k * B[2];
+  const Real us = w0 * t0 + w1 * t1 + w2 * t2;
+  const Real tau2 = t0 * t0 + t1 * t1 + t2 * t2;
+  const Real sig = (Real)1 + w0 * w0 + w1 * w1 + w2 * w2 - tau2;
+  const Real gn = sqrt_r((Real)0.5 * (sig + sqrt_r(sig * sig + (Real)4 * (tau2 + us * us))));
+  const Real ign = (Real)1 / gn;
+  const Real a0 = t0 * ign, a1 = t1 * ign, a2 = t2 * ign;
+  const Real sf = (Real)1 / ((Real)1 + a0 * a0 + a1 * a1 + a2 * a2);
+  const Real wa = w0 * a0 + w1 * a1 + w2 * a2;
+  u[0] = sf * (w0 + wa * a0 + (w1 * a2 - w2 * a1));
+  u[1] = sf * (w1 + wa * a1 + (w2 * a0 - w0 * a2));
+  u[2] = sf * (w2 + wa * a2 + (w0 * a1 - w1 * a0));
+}
+
+// Hybrid pusher (Sec. 5.2): a particle whose fields are drift dominated
+// (|E| < e_ovr |B|) and whose nominal gyroradius |u| m rho0 / (|q| |B|) =
+// |u| dt / (2 |k| |B|) is below the critical length follows its guiding
+// centre: the momentum perpendicular to B is dropped, the parallel
+// four-velocity takes the kick 2k E.b, and u = u_par b + gamma v_E with
+// v_E = E x B / B^2 and gamma = sqrt((1 + u_par^2) / (1 - v_E^2)).  The
+// regime test is taken in FP64.
+template <class Real>
+__device__ __forceinline__ bool gca_regime(double k, double dt, double e_ovr, double larmor_max,
+                                           const Real E[3], const Real B[3], const Real u[3]) {
+  const double e2 = (double)E[0] * E[0] + (double)E[1] * E[1] + (double)E[2] * E[2];
+  const double b2 = (double)B[0] * B[0] + (double)B[1] * B[1] + (double)B[2] * B[2];
+  if (!(b2 > 0.0) || !(e2 < e_ovr * e_ovr * b2)) return false;
+  const double ua = sqrt((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
+  return ua * dt / (2.0 * fabs(k) * sqrt(b2)) < larmor_max;
+}
+
+template <class Real>
+__device__ __forceinline__ void gca_push(Real k, const Real E[3], const Real B[3], Real u[3]) {
+  const Real b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  const Real ib = rsqrt_r(b2), ib2 = (Real)1 / b2;
+  const Real bx = B[0] * ib, by = B[1] * ib, bz = B[2] * ib;
+  const Real e0 = (E[1] * B[2] - E[2] * B[1]) * ib2;
+  const Real e1 = (E[2] * B[0] - E[0] * B[2]) * ib2;
+  const Real e2 = (E[0] * B[1] - E[1] * B[0]) * ib2;
+  const Real up = u[0] * bx + u[1] * by + u[2] * bz + (Real)2 * k * (E[0] * bx + E[1] * by + E[2] * bz);
+  const Real ve2 = e0 * e0 + e1 * e1 + e2 * e2;
+  const Real gm = sqrt_r(((Real)1 + up * up) / ((Real)1 - ve2));
+  u[0] = up * bx + gm * e0;
+  u[1] = up * by + gm * e1;
+  u[2] = up * bz + gm * e2;
+}
+
+// The species' pusher (SpeciesTable::pusher: 0 Boris, 1 Vay, +2 the
+// guiding-centre hybrid).
+template <class Real>
+__device__ __forceinline__ void push_momentum(const SpeciesTable &sp, int s, Real k, double dt,
+                                              const Real E[3], const Real B[3], Real u[3]) {
+  const int pk = sp.pusher[s];
+  if ((pk & 2) && gca_regime<Real>(sp.k[s], dt, sp.gca_e_ovr[s], sp.gca_larmor[s], E, B, u)) {
+    gca_push(k, E, B, u);
+  } else if (pk & 1) {
+    vay(k, E, B, u);
+  } else {
+    boris(k, E, B, u);
+  }
+}
+
+// Reverse of the Boris push ("reverse Boris rotation"): dL/du_new -> dL/du,
+// dL/dE, dL/dB (global Cartesian), from the recorded intermediates.
+template <class Real>
+__device__ __forceinline__ void boris_rev(Real k, const BorisRec<Real> &R, const Real unb[3],
+                                          Real ub[3], Real Eb[3], Real Bb[3]) {
+  const Real *um = R.um, *t = R.t, *s3 = R.s, *up = R.up;
+  Real umb[3], upb[3], sb[3], tb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Eb[a] = k * unb[a];  // u+ = u+' + k E
+    umb[a] = unb[a];     // u+' = um + up x s
+  }
+  // up x s: upb += s x unb, sb = unb x up
+  upb[0] = s3[1] * unb[2] - s3[2] * unb[1];
+  upb[1] = s3[2] * unb[0] - s3[0] * unb[2];
+  upb[2] = s3[0] * unb[1] - s3[1] * unb[0];
+  sb[0] = unb[1] * up[2] - unb[2] * up[1];
+  sb[1] = unb[2] * up[0] - unb[0] * up[2];
+  sb[2] = unb[0] * up[1] - unb[1] * up[0];
+  // up = um + um x t: umb += upb + t x upb, tb = upb x um
+#pragma unroll
+  for (int a = 0; a < 3; ++a) umb[a] += upb[a];
+  umb[0] += t[1] * upb[2] - t[2] * upb[1];
+  umb[1] += t[2] * upb[0] - t[0] * upb[2];
+  umb[2] += t[0] * upb[1] - t[1] * upb[0];
+  tb[0] = upb[1] * um[2] - upb[2] * um[1];
+  tb[1] = upb[2] * um[0] - upb[0] * um[2];
+  tb[2] = upb[0] * um[1] - upb[1] * um[0];
+  // s = t sf, sf = 2 / (1 + t.t)
+  const Real ts = t[0] * sb[0] + t[1] * sb[1] + t[2] * sb[2];
+  const Real c4 = (Real)4 / (((Real)1 + R.tt) * ((Real)1 + R.tt));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) tb[a] += R.sf * sb[a] - c4 * t[a] * ts;
+  // t = k B / gm
+  Real gmb = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Bb[a] = k * R.igm * tb[a];
+    gmb -= t[a] * tb[a] * R.igm;
+  }
+  // gm = sqrt(1 + um.um); um = u + k E
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    umb[a] += gmb * um[a] * R.igm;
+    Eb[a] += k * umb[a];
+    ub[a] = umb[a];
+  }
 }
 
 // Cartesian in-cell displacement dt u_a / (gamma Delta_a) (steps 6-7); the
@@ -532,6 +676,281 @@ __device__ __forceinline__ void axi_move(const GridConst &g, const AxiMetric<CT>
     }
     dx2 = s * (CT)(1.0 / g.dT);
   }
+}
+
+
+// Tetrad and rotation (Sec. 2.3 step 4): F^i_hat = sqrt(h_ii) F^i at x_p
+// (eq. curvspace-tetradtrans), then (r, theta, phi)_hat -> (x, y, z)_hat at
+// the particle's theta and azimuth.
+template <class CT, class Real>
+__device__ __forceinline__ void axi_to_cart(const AxiMetric<CT> &M, CT sp, CT cp, const Real F[6],
+                                            Real E[3], Real B[3]) {
+  const CT h[3] = {M.h1, M.h2, M.h3};
+  CT Fh[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Fh[c] = (CT)F[c] * h[c % 3];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const CT a = Fh[3 * f], b = Fh[3 * f + 1], cc = Fh[3 * f + 2];
+    const CT ax = a * M.st + b * M.ct;  // cylindrical radial component
+    Real *out = f ? B : E;
+    out[0] = (Real)(ax * cp - cc * sp);
+    out[1] = (Real)(ax * sp + cc * cp);
+    out[2] = (Real)(a * M.ct - b * M.st);
+  }
+}
+
+// Axisymmetric particle (Sec. 2.3 steps 4-7): tetrad and rotation, Boris in
+// the global basis, offset-relative move.  Metric and move run in CT (FP64
+// near the axis and r_min when Real is float).
+// PUSHERS: the species may use another pusher than Boris (push_momentum).
+template <int GEOM, class CT, class Real, class D, bool PUSHERS = false>
+__device__ __forceinline__ void axi_particle(const GridConst &g, const SpeciesTable &sp, int s,
+                                             double dt, int i1, int i2, D d1, D d2, Real phi,
+                                             const Real F[6], Real u[3], CT &dx1, CT &dx2,
+                                             CT &dphi) {
+  const Real k = (Real)sp.k[s];
+  const CT x1 = (CT)i1 + (CT)d1;
+  const CT x2 = (CT)i2 + (CT)d2;
+  const AxiMetric<CT> M = axi_metric<GEOM, CT>(g, x1, x2);
+  CT sp_, cp;
+  sincos_r((CT)phi, &sp_, &cp);
+  Real E[3], B[3];
+  axi_to_cart<CT, Real>(M, sp_, cp, F, E, B);
+  if (PUSHERS)
+    push_momentum<Real>(sp, s, k, dt, E, B, u);
+  else
+    boris(k, E, B, u);
+  const CT uu0 = (CT)u[0], uu1 = (CT)u[1], uu2 = (CT)u[2];
+  const CT gi = rsqrt_r((CT)1 + uu0 * uu0 + uu1 * uu1 + uu2 * uu2);
+  const CT dtg = (CT)dt * gi;
+  axi_move<GEOM, CT>(g, M, x2, sp_, cp, dtg * uu0, dtg * uu1, dtg * uu2, dx1, dx2, dphi);
+}
+
+template <class Real, class CT>
+__device__ __forceinline__ Real next_phi(Real phi, CT dphi) {
+  CT pn = (CT)phi + dphi;
+  const CT twopi = (CT)(2.0 * kPI);
+  if (pn < (CT)0) pn += twopi;
+  if (pn >= twopi) pn -= twopi;
+  Real pr = (Real)pn;
+  if (pr >= (Real)(2.0 * kPI)) pr = (Real)0;
+  return pr;
+}
+
+// ---------------------------------------------------------------- reverse (adjoint) pieces
+// Adjoint of the metric quantities with respect to the code position.
+template <class CT>
+struct AxiMetricBar {
+  CT r, th, h1, h2, h3, st, ct;
+};
+
+// (r, theta, sqrt h_ii, sin, cos) at (x1, x2) -> (dL/dx1, dL/dx2); the
+// Sec. 2.4 metric differentiated by hand
+template <int GEOM, class CT>
+__device__ __forceinline__ void axi_metric_rev(const GridConst &g, const AxiMetric<CT> &M, CT x2,
+                                               AxiMetricBar<CT> b, CT &x1b, CT &x2b) {
+  // h3 = r sin(theta); st, ct = sin, cos of theta
+  b.r += b.h3 * M.st;
+  b.st += b.h3 * M.r;
+  b.th += b.st * M.ct - b.ct * M.st;
+  if (GEOM == 1) {
+    // r = rmin + x1 dr, theta = x2 dth, h1 = dr, h2 = r dth
+    b.r += b.h2 * (CT)g.dth;
+    x1b += b.r * (CT)g.dr;
+    x2b += b.th * (CT)g.dth;
+  } else {
+    // r = r0 + e^R, R = Rmin + x1 dR; h1 = dR e^R; h2 = dT theta_T(T) r; T = x2 dT
+    const CT eR = M.r - (CT)g.r0;
+    const CT T = x2 * (CT)g.dT;
+    const CT tp = T * (CT)(1.0 / kPI);
+    const CT vt = (CT)g.vt;
+    const CT thT = (CT)1 + (CT)2 * vt + (CT)12 * vt * tp * (tp - (CT)1);
+    const CT thTT = (CT)12 * vt * ((CT)2 * tp - (CT)1) * (CT)(1.0 / kPI);
+    b.r += b.h2 * (CT)g.dT * thT;
+    const CT thTb = b.h2 * (CT)g.dT * M.r;
+    const CT eRb = b.r + b.h1 * (CT)g.dR;
+    x1b += eRb * eR * (CT)g.dR;
+    x2b += (b.th * thT + thTb * thTT) * (CT)g.dT;
+  }
+}
+
+// Reverse of axi_move: given dL/d(dx1, dx2, dphi), accumulate dL/d of its
+// inputs: the position (through the metric: into Mb and x2b), the azimuth
+// (through sin, cos: spb, cpb) and the Cartesian displacement (DXb).  The
+// intermediates are recomputed; the qsph Newton solve is differentiated as
+// its converged root (implicit function theorem).
+template <int GEOM, class CT>
+__device__ __forceinline__ void axi_move_rev(const GridConst &g, const AxiMetric<CT> &M, CT x2,
+                                             CT sp, CT cp, CT DX, CT DY, CT DZ, CT dx1b, CT dx2b,
+                                             CT dphib, AxiMetricBar<CT> &Mb, CT &x2b, CT &spb,
+                                             CT &cpb, CT DXb[3]) {
+  const CT Dr = DX * cp + DY * sp;
+  const CT Dp = DY * cp - DX * sp;
+  const CT rho_o = M.r * M.st, z_o = M.r * M.ct;
+  const CT D2 = DX * DX + DY * DY + DZ * DZ;
+  const CT ir2 = (CT)1 / (M.r * M.r);
+  const CT P = (CT)2 * (rho_o * Dr + z_o * DZ) + D2;
+  const CT sig = P * ir2;
+  const CT hl = (CT)0.5 * log1p_r(sig);
+  const CT rx = rho_o + Dr;
+  const CT rho_n = sqrt_r(rx * rx + Dp * Dp);
+  const CT z_n = z_o + DZ;
+  // adjoints of the intermediates
+  CT hlb = 0, dthb = 0;
+  CT rb = 0;
+  if (GEOM == 1) {
+    const CT E1 = expm1_r(hl);
+    rb += dx1b * E1 * (CT)(1.0 / g.dr);
+    hlb += dx1b * M.r * (CT)(1.0 / g.dr) * (E1 + (CT)1);
+    dthb += dx2b * (CT)(1.0 / g.dth);
+  } else {
+    if (g.r0 == 0.0) {
+      hlb += dx1b * (CT)(1.0 / g.dR);
+    } else {
+      const CT E1 = expm1_r(hl);
+      const CT den = M.r - (CT)g.r0;
+      const CT Q = M.r * E1 / den;
+      const CT Qb = dx1b * (CT)(1.0 / g.dR) / ((CT)1 + Q);
+      rb += Qb * E1 * (-(CT)g.r0) / (den * den);
+      hlb += Qb * M.r / den * (E1 + (CT)1);
+    }
+    // s solves a1 s + a2 s^2 + a3 s^3 = dth (T0 = x2 dT); dx2 = s / dT
+    const CT T0 = x2 * (CT)g.dT;
+    const CT tp = T0 * (CT)(1.0 / kPI);
+    const CT vt = (CT)g.vt;
+    const CT a1 = (CT)1 + (CT)2 * vt + (CT)12 * vt * tp * (tp - (CT)1);
+    const CT a2 = (CT)(6.0 / (kPI * kPI)) * vt * ((CT)2 * T0 - (CT)kPI);
+    const CT a3 = (CT)(4.0 / (kPI * kPI)) * vt;
+    // the forward's dth and its Newton root
+    CT dth;
+    {
+      const CT drho0 = ((CT)2 * rho_o * Dr + Dr * Dr + Dp * Dp);
+      if (rho_n + rho_o > (CT)0)
+        dth = atan2_r(drho0 / (rho_n + rho_o) * z_o - DZ * rho_o, rho_o * rho_n + z_o * z_n);
+      else
+        dth = ((CT)(kPI / 2) - atan2_r(z_n, rho_n)) - M.th;
+    }
+    CT s = dth / a1;
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+      const CT f = ((a3 * s + a2) * s + a1) * s - dth;
+      const CT fp = ((CT)3 * a3 * s + (CT)2 * a2) * s + a1;
+      s = s - f / fp;
+    }
+    const CT fp = ((CT)3 * a3 * s + (CT)2 * a2) * s + a1;
+    const CT sb = dx2b * (CT)(1.0 / g.dT);
+    dthb += sb / fp;
+    const CT a1b = -sb * s / fp, a2b = -sb * s * s / fp;
+    const CT T0b = a1b * (CT)12 * vt * ((CT)2 * tp - (CT)1) * (CT)(1.0 / kPI) +
+                   a2b * (CT)(12.0 / (kPI * kPI)) * vt;
+    x2b += T0b * (CT)g.dT;
+  }
+  // dphi = atan2(Dp, rx)
+  CT Dpb = 0, rxb = 0, Drb = 0, rhoob = 0, zob = 0, rhonb = 0, znb = 0, DZb = 0;
+  {
+    const CT q2 = Dp * Dp + rx * rx;
+    if (q2 > (CT)0) {
+      Dpb += dphib * rx / q2;
+      rxb -= dphib * Dp / q2;
+    }
+  }
+  if (rho_n + rho_o > (CT)0) {
+    const CT den = rho_n + rho_o;
+    const CT num = (CT)2 * rho_o * Dr + Dr * Dr + Dp * Dp;
+    const CT drho = num / den;
+    const CT Y = drho * z_o - DZ * rho_o;
+    const CT X = rho_o * rho_n + z_o * z_n;
+    const CT q2 = X * X + Y * Y;
+    const CT Yb = dthb * X / q2, Xb = -dthb * Y / q2;
+    const CT drhob = Yb * z_o;
+    zob += Yb * drho + Xb * z_n;
+    DZb -= Yb * rho_o;
+    rhoob += -Yb * DZ + Xb * rho_n;
+    rhonb += Xb * rho_o;
+    znb += Xb * z_o;
+    const CT numb = drhob / den;
+    const CT denb = -drhob * drho / den;
+    rhonb += denb;
+    rhoob += denb;
+    rhoob += numb * (CT)2 * Dr;
+    Drb += numb * (CT)2 * (rho_o + Dr);
+    Dpb += numb * (CT)2 * Dp;
+  } else {  // both points on the axis: theta from the literal map
+    const CT q2 = z_n * z_n + rho_n * rho_n;
+    if (q2 > (CT)0) {
+      znb -= dthb * rho_n / q2;
+      rhonb += dthb * z_n / q2;
+    }
+    Mb.th -= dthb;
+  }
+  // z_n = z_o + DZ; rho_n = |(rx, Dp)|
+  zob += znb;
+  DZb += znb;
+  if (rho_n > (CT)0) {
+    rxb += rhonb * rx / rho_n;
+    Dpb += rhonb * Dp / rho_n;
+  }
+  // rx = rho_o + Dr
+  rhoob += rxb;
+  Drb += rxb;
+  // hl = log1p(sig) / 2, sig = P / r^2
+  const CT sigb = hlb * (CT)0.5 / ((CT)1 + sig);
+  const CT Pb = sigb * ir2;
+  rb -= (CT)2 * sigb * sig / M.r;
+  rhoob += (CT)2 * Pb * Dr;
+  Drb += (CT)2 * Pb * rho_o;
+  zob += (CT)2 * Pb * DZ;
+  DZb += (CT)2 * Pb * z_o;
+  DXb[0] += (CT)2 * Pb * DX;
+  DXb[1] += (CT)2 * Pb * DY;
+  DZb += (CT)2 * Pb * DZ;
+  // rho_o = r sin(theta), z_o = r cos(theta)
+  rb += rhoob * M.st + zob * M.ct;
+  Mb.st += rhoob * M.r;
+  Mb.ct += zob * M.r;
+  Mb.r += rb;
+  // Dr = DX cp + DY sp, Dp = DY cp - DX sp
+  DXb[0] += Drb * cp - Dpb * sp;
+  DXb[1] += Drb * sp + Dpb * cp;
+  DXb[2] += DZb;
+  cpb += Drb * DX + Dpb * DY;
+  spb += Drb * DY - Dpb * DX;
+}
+
+// Reverse of axi_to_cart: dL/dE, dL/dB (global Cartesian) -> dL/dF (the
+// interpolated contravariant components) and the metric / azimuth adjoints.
+template <class CT, class Real>
+__device__ __forceinline__ void axi_to_cart_rev(const AxiMetric<CT> &M, CT sp, CT cp,
+                                                const Real F[6], const Real Eb[3],
+                                                const Real Bb[3], Real Fb[6],
+                                                AxiMetricBar<CT> &Mb, CT &spb, CT &cpb) {
+  const CT h[3] = {M.h1, M.h2, M.h3};
+  CT hb[3] = {0, 0, 0};
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const Real *ob = f ? Bb : Eb;
+    const CT o0 = (CT)ob[0], o1 = (CT)ob[1], o2 = (CT)ob[2];
+    const CT a = (CT)F[3 * f] * h[0], b = (CT)F[3 * f + 1] * h[1], cc = (CT)F[3 * f + 2] * h[2];
+    const CT ax = a * M.st + b * M.ct;
+    const CT axb = o0 * cp + o1 * sp;
+    const CT ccb = -o0 * sp + o1 * cp;
+    cpb += o0 * ax + o1 * cc;
+    spb += -o0 * cc + o1 * ax;
+    const CT ab = axb * M.st + o2 * M.ct;
+    const CT bb = axb * M.ct - o2 * M.st;
+    Mb.st += axb * a - o2 * b;
+    Mb.ct += axb * b + o2 * a;
+    Fb[3 * f] = (Real)(ab * h[0]);
+    Fb[3 * f + 1] = (Real)(bb * h[1]);
+    Fb[3 * f + 2] = (Real)(ccb * h[2]);
+    hb[0] += ab * (CT)F[3 * f];
+    hb[1] += bb * (CT)F[3 * f + 1];
+    hb[2] += ccb * (CT)F[3 * f + 2];
+  }
+  Mb.h1 += hb[0];
+  Mb.h2 += hb[1];
+  Mb.h3 += hb[2];
 }
 
 }  // namespace picstep

@@ -89,6 +89,7 @@ def lib():
             "pic_set_stream": [vp, vp],
             "pic_timestep_from_cfl": [vp, dbl, C.POINTER(dbl)],
             "pic_species_add": [vp, dbl, dbl, u64, C.POINTER(i32)],
+            "pic_species_set_pusher": [vp, i32, i32, dbl, dbl],
             "pic_fields_set": [vp, vp, i32, i32],
             "pic_fields_fill_ghosts": [vp],
             "pic_particles_load": [vp, i32, u64, vp, vp, vp, vp, vp],
@@ -198,6 +199,12 @@ class Context:
                     "species_add")
         self.species.append((q, m, capacity))
         return sid.value
+
+    def species_set_pusher(self, s, pusher="boris", gca=False, e_ovr=0.9, larmor_max=0.0):
+        """pusher "boris" or "vay"; gca=True adds the guiding-centre hybrid."""
+        code = {"boris": 0, "vay": 1}[pusher] | (2 if gca else 0)
+        self._check(lib().pic_species_set_pusher(self.h, int(s), code, float(e_ovr),
+                                                 float(larmor_max)), "species_set_pusher")
 
     def bind(self, stream=None):
         """Allocate every device buffer with torch and register it."""
@@ -423,8 +430,12 @@ def from_workload(wl, prec="f32", device="cuda", sort_every=None, fp64_axis_cell
                   periodic=wl.periodic, rho0=wl.rho0, prec=prec, fp64_axis_cells=fp64_axis_cells,
                   sort_every=wl.sort_every if sort_every is None else sort_every,
                   max_particles=sum(caps), device=device)
-    for s, cap in zip(wl.species, caps):
+    for i, (s, cap) in enumerate(zip(wl.species, caps)):
         ctx.species_add(s["q"], s["m"], cap)
+        code = int(s.get("pusher", 0))
+        if code:
+            ctx.species_set_pusher(i, "vay" if code & 1 else "boris", gca=bool(code & 2),
+                                   e_ovr=s.get("e_ovr", 0.9), larmor_max=s.get("larmor_max", 0.0))
     ctx.bind()
     ctx.fields_set(wl.fields_tetrad, "tetrad", wl.fields_includes_ghosts)
     for i, s in enumerate(wl.species):

@@ -265,3 +265,127 @@ def test_autograd_function_matches_direct_backward():
     for s, lam in enumerate(lam_u):
         o = L.species_offset[s]
         np.testing.assert_array_equal(du0[:, o:o + lam.shape[0]].T, ref[1][s])
+
+
+# --------------------------------------------------------------------------- axisymmetric
+def _axi_case(geom, K, seed, sort_every=20):
+    """A small hot plasma on a log-r grid reaching r = 3 (cells of ~0.06):
+    particles cross cells every few steps, some leave radially, and the
+    stretched grid (vartheta = 0.3) is exercised by the quasi-spherical one."""
+    vt = 0.3 if geom == "qsph" else 0.0
+    wl = W.curvilinear(geom, 32, 16, 3.0, vt, ppc=3, theta=2.0, density_power=0, steps=K,
+                       seed=seed)
+    wl.sort_every = sort_every
+    return wl
+
+
+def _axi_weights(wl, seed):
+    """dL/dJ on every node, ghosts included (curvilinear ghosts keep the
+    current of radially exiting particles)."""
+    rng = np.random.default_rng(seed)
+    lamJ = rng.uniform(-1, 1, size=(3,) + wl.padded_shape())
+    lam_u = [rng.normal(size=(s["cell"].shape[0], 3)) for s in wl.species]
+    return lamJ, lam_u
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("geom,K,m", [("sph", 1, 1), ("qsph", 1, 1), ("sph", 4, 2), ("qsph", 4, 2)])
+def test_adjoint_axisymmetric_matches_reference(geom, K, m, prec):
+    print(f"[adjoint] {geom} K={K} m={m} {prec}", flush=True)
+    wl = _axi_case(geom, K, 60 + K)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    lamJ, lam_u = _axi_weights(wl, 13)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    ref = O.adjoint(g, dt, K, EB, wl.species, lamJ, lam_u=lam_u)
+    dEB, du, J, ctx, _ = _gpu_grad(wl, prec, K, m, lamJ, lam_u)
+    out, Jref = O.run(g, dt, K, EB, wl.species)
+    dead = sum(int((s["alive"] == 0).sum()) for s in out)
+    eJ = U.rel_l2(J, Jref)
+    eE = U.rel_l2(dEB, ref["dEB"])
+    eu = U.rel_l2(np.concatenate(du), np.concatenate(ref["du0"]))
+    print(f"  J {eJ:.2e} dEB {eE:.2e} du0 {eu:.2e} ({dead} particles left radially)", flush=True)
+    tol = (1e-12 if K == 1 else 1e-10) if prec == "f64" else (1e-5 if K == 1 else 1e-3)
+    assert eJ < max(tol, 1e-5 if prec == "f32" else tol)
+    assert eE < tol, eE
+    assert eu < tol, eu
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_axisymmetric_with_sorts(prec):
+    """Sorts every 2 steps inside K = 6 steps checkpointed every 4 on the
+    stretched quasi-spherical grid: the azimuth adjoints follow the sorts
+    back with the momentum and offset adjoints."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[adjoint] qsph sorts inside {prec}", flush=True)
+    K, m, S = 6, 4, 2
+    wl = _axi_case("qsph", K, 71, sort_every=S)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    lamJ, lam_u = _axi_weights(wl, 14)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    ref = O.adjoint(g, dt, K, EB, wl.species, lamJ, lam_u=lam_u)
+    ctx = P.from_workload(wl, prec=prec, sort_every=S)
+    ctx.forward_checkpointed(dt, K, m)
+    L = ctx.layout()
+    order = ctx.checkpointed_order()
+    lu0 = np.zeros((3, L.capacity))
+    for s, lam in enumerate(lam_u):
+        o = L.species_offset[s]
+        lu0[:, o:o + lam.shape[0]] = lam.T
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    lu = torch.from_numpy(lu0[:, order].copy()).to(dtype=dtype, device="cuda")
+    dEB, du0 = ctx.backward(dt, K, m, torch.from_numpy(lamJ).to(dtype=dtype, device="cuda"), lu)
+    dEB = dEB.double().cpu().numpy()
+    du0 = du0.double().cpu().numpy()
+    du = [du0[:, L.species_offset[s]:L.species_offset[s] + lam.shape[0]].T
+          for s, lam in enumerate(lam_u)]
+    eE = U.rel_l2(dEB, ref["dEB"])
+    eu = U.rel_l2(np.concatenate(du), np.concatenate(ref["du0"]))
+    print(f"  dEB {eE:.2e} du0 {eu:.2e}", flush=True)
+    tol = 1e-10 if prec == "f64" else 1e-3
+    assert eE < tol, eE
+    assert eu < tol, eu
+
+
+@pytest.mark.parametrize("geom", ["sph", "qsph"])
+def test_adjoint_axisymmetric_central_differences(geom):
+    """FP64: <grad, v> against central differences of the GPU forward map
+    (fields on every padded node, and the initial momenta)."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[adjoint] {geom} finite differences", flush=True)
+    K, m = 5, 2
+    wl = _axi_case(geom, K, 80, sort_every=0)
+    lamJ, lam_u = _axi_weights(wl, 15)
+    rng = np.random.default_rng(16)
+    dEB, du, _, ctx, dt = _gpu_grad(wl, "f64", K, m, lamJ, lam_u)
+    g, EB0 = U.oracle_fields(wl, "f64")
+    L = ctx.layout()
+
+    def loss(EBx, du_dir, h):
+        c = P.from_workload(wl, prec="f64", sort_every=0)
+        c.fields().copy_(torch.from_numpy(EBx).cuda())
+        arr = c.particle_arrays()
+        for s, d in enumerate(du_dir):
+            o = L.species_offset[s]
+            for a in range(3):
+                arr["u"][a][o:o + d.shape[0]] += torch.from_numpy(h * d[:, a]).cuda()
+        c.push_deposit(dt, K)
+        J = c.current_host()
+        uu = [c.particles_get(s)["u"] for s in range(len(wl.species))]
+        return float(np.sum(lamJ * J) + sum(np.sum(l * x) for l, x in zip(lam_u, uu)))
+
+    for trial in range(2):
+        vE = rng.normal(size=EB0.shape) * np.abs(EB0).max()
+        vu = [rng.normal(size=(s["cell"].shape[0], 3)) for s in wl.species]
+        h = 1e-7
+        fd = (loss(EB0 + h * vE, vu, h) - loss(EB0 - h * vE, vu, -h)) / (2 * h)
+        ip = np.sum(dEB * vE) + sum(np.sum(a * b) for a, b in zip(du, vu))
+        print(f"  trial {trial}: grad.v {ip:.10e} fd {fd:.10e}", flush=True)
+        assert ip == pytest.approx(fd, rel=1e-6, abs=1e-9)

@@ -236,8 +236,11 @@ def _run_case(name, prec, checkpoints, boxes, whole, nsample, cold_first=False):
             print(f"  continuity residual {c:.2e}", flush=True)
             assert c <= tol["cont"], c
         else:
+            # particles dead before the step (outside the radial range) did not move
+            was_alive = (pc[:, 0] >= 0) & (pc[:, 0] < wl.n[0])
             for lo, size in boxes:
                 sel = _box_sel(wl, {"cell": pc}, lo, size)
+                sel = sel[was_alive[sel]]
                 c = checks.continuity_residual_box(Jg, wl.n, wl.dim, cart, dt,
                                                    (pc[sel], po[sel]), (nc[sel], no[sel]),
                                                    qw[sel], _box_nodes(wl, lo, size)[1:])
