@@ -817,6 +817,211 @@ int32_t sort_key(const Grid &G, const int32_t *c, int32_t alive) {
   return (int32_t)(brick * (B[0] * B[1] * B[2]) + local);
 }
 
+// ---------------------------------------------------------------- field solver
+// The field update around the particle step (Sec. 2.3 steps 2, 9-11), on the
+// Yee lattice of App. A with the metric of Sec. 2.4: Faraday's and Ampere's
+// laws in the discretized forms of App. A (covariant components
+// F_i = h_ii F^i differenced over unit code-coordinate cells, divided by
+// sqrt(h) = sqrt(h11 h22 h33) at the updated component's point), the axis
+// rules of Sec. 2.6 on (quasi-)spherical grids, and the digital filter of
+// Sec. 2.5.  `coupling` is the factor in front of the conformal current in
+// Ampere's law (4 pi in the paper's units).
+
+// sqrt(h_ii)^2 and sqrt(h) at code coordinates (x3 plays no role)
+double h_comp(const Grid &G, int a, double x1, double x2) {
+  double h[3];
+  sqrt_h(G, x1, x2, h);
+  return h[a] * h[a];
+}
+double sqrt_det_h(const Grid &G, double x1, double x2) {
+  double h[3];
+  sqrt_h(G, x1, x2, h);
+  return h[0] * h[1] * h[2];
+}
+
+// node ranges updated by the solver, per component stagger: periodic
+// Cartesian [0, N); (quasi-)spherical along x1 and x2: nodes [0, N] for an
+// integer stagger, cells [0, N) for a half stagger (ghosts are the caller's)
+void node_range(const Grid &G, int dim, double stag, int &lo, int &hi) {
+  lo = 0;
+  if (dim >= G.dim) {
+    hi = 1;
+    return;
+  }
+  if (G.geom == 0)
+    hi = G.n[dim];
+  else
+    hi = (stag == 0.0) ? G.n[dim] + 1 : G.n[dim];
+}
+
+// covariant component m of field block f (0: E, 1: B) at array element (i,j,k)
+double cov(const Grid &G, const double *EB, int f, int m, int i, int j, int k) {
+  const int c = 3 * f + m;
+  const double x1 = i + STAG[c][0], x2 = j + STAG[c][1];
+  return h_comp(G, m, x1, x2) * EB[pidx(G, c, i, j, k)];
+}
+
+bool on_axis(const Grid &G, int j) { return G.geom != 0 && (j == 0 || j == G.n[1]); }
+
+// B^i -= f * (curl E)^i / sqrt(h) (App. A, eq. discretized-faraday); f = dt/2
+// for each of the two half steps of the loop
+void faraday(const Grid &G, double *EB, double f) {
+  std::vector<double> out(EB + 3 * G.npts, EB + 6 * G.npts);
+  const bool d3 = G.dim == 3;
+  for (int c = 3; c < 6; ++c) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) node_range(G, dd, STAG[c][dd], lo[dd], hi[dd]);
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) {
+          if (c == 4 && on_axis(G, j)) continue;  // B2 on the axis stays 0 (Sec. 2.6)
+          double curl = 0.0;
+          if (c == 3) {  // B1 at (i, j+1/2, k+1/2)
+            curl = cov(G, EB, 0, 2, i, j + 1, k) - cov(G, EB, 0, 2, i, j, k);
+            if (d3) curl -= cov(G, EB, 0, 1, i, j, k + 1) - cov(G, EB, 0, 1, i, j, k);
+          } else if (c == 4) {  // B2 at (i+1/2, j, k+1/2)
+            curl = -(cov(G, EB, 0, 2, i + 1, j, k) - cov(G, EB, 0, 2, i, j, k));
+            if (d3) curl += cov(G, EB, 0, 0, i, j, k + 1) - cov(G, EB, 0, 0, i, j, k);
+          } else {  // B3 at (i+1/2, j+1/2, k)
+            curl = (cov(G, EB, 0, 1, i + 1, j, k) - cov(G, EB, 0, 1, i, j, k)) -
+                   (cov(G, EB, 0, 0, i, j + 1, k) - cov(G, EB, 0, 0, i, j, k));
+          }
+          const double sh = sqrt_det_h(G, i + STAG[c][0], j + STAG[c][1]);
+          out[pidx(G, c - 3, i, j, k)] = EB[pidx(G, c, i, j, k)] - f * curl / sh;
+        }
+  }
+  for (int c = 3; c < 6; ++c) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) node_range(G, dd, STAG[c][dd], lo[dd], hi[dd]);
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) {
+          if (c == 4 && on_axis(G, j)) {
+            EB[pidx(G, c, i, j, k)] = 0.0;
+            continue;
+          }
+          EB[pidx(G, c, i, j, k)] = out[pidx(G, c - 3, i, j, k)];
+        }
+  }
+  fill_periodic_ghosts(G, EB + 3 * G.npts, 3);
+}
+
+// Sec. 2.6: A(x1) = integral over x2 in [0, 1/2] of sqrt(h), in the paper's
+// closed forms: spherical r^2 dr (1 - cos(dtheta/2)); quasi-spherical
+// (r0 + e^R)^2 e^R dR (1 - cos(theta(dT/2)))
+double polar_area(const Grid &G, double x1) {
+  if (G.geom == 1) {
+    const double r = G.lo[0] + x1 * G.dr;
+    return r * r * G.dr * (1.0 - std::cos(0.5 * G.dth));
+  }
+  const double eR = std::exp(G.Rmin + x1 * G.dR);
+  const double r = G.r0 + eR;
+  const double tt = 0.5 * G.dT + G.vt * G.dT * (1.0 - G.dT / PI) * (1.0 - G.dT / (2.0 * PI));
+  return r * r * eR * G.dR * (1.0 - std::cos(tt));
+}
+
+// E^i += dt (curl B)^i / sqrt(h) - coupling dt J^i / sqrt(h) (App. A,
+// eq. discretized-ampere); on the axis nodes E3 = 0 and E1 takes the
+// integrated form (Sec. 2.6)
+void ampere(const Grid &G, double *EB, const double *J, double dt, double coupling) {
+  std::vector<double> out(EB, EB + 3 * G.npts);
+  const bool d3 = G.dim == 3;
+  const double *Bv = EB;  // covariant B through cov(.., f = 1, ..)
+  for (int c = 0; c < 3; ++c) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) node_range(G, dd, STAG[c][dd], lo[dd], hi[dd]);
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) {
+          const double Jc = J[pidx(G, c, i, j, k)];
+          double v;
+          if (c == 2 && on_axis(G, j)) {
+            v = 0.0;
+          } else if (c == 0 && on_axis(G, j)) {
+            // integrated over the half cell next to the axis: A dE1/dt =
+            // +-B_3 at the half node inside - (coupling / 2) J1
+            const double A = polar_area(G, i + 0.5);
+            const double b3 = (j == 0) ? cov(G, Bv, 1, 2, i, 0, k) : -cov(G, Bv, 1, 2, i, j - 1, k);
+            v = EB[pidx(G, c, i, j, k)] + dt * (b3 - 0.5 * coupling * Jc) / A;
+          } else {
+            double curl;
+            if (c == 0) {  // E1 at (i+1/2, j, k)
+              curl = cov(G, Bv, 1, 2, i, j, k) - cov(G, Bv, 1, 2, i, j - 1, k);
+              if (d3) curl -= cov(G, Bv, 1, 1, i, j, k) - cov(G, Bv, 1, 1, i, j, k - 1);
+            } else if (c == 1) {  // E2 at (i, j+1/2, k)
+              curl = -(cov(G, Bv, 1, 2, i, j, k) - cov(G, Bv, 1, 2, i - 1, j, k));
+              if (d3) curl += cov(G, Bv, 1, 0, i, j, k) - cov(G, Bv, 1, 0, i, j, k - 1);
+            } else {  // E3 at (i, j, k+1/2)
+              curl = (cov(G, Bv, 1, 1, i, j, k) - cov(G, Bv, 1, 1, i - 1, j, k)) -
+                     (cov(G, Bv, 1, 0, i, j, k) - cov(G, Bv, 1, 0, i, j - 1, k));
+            }
+            const double sh = sqrt_det_h(G, i + STAG[c][0], j + STAG[c][1]);
+            v = EB[pidx(G, c, i, j, k)] + dt * (curl - coupling * Jc) / sh;
+          }
+          out[pidx(G, c, i, j, k)] = v;
+        }
+  }
+  for (int c = 0; c < 3; ++c) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) node_range(G, dd, STAG[c][dd], lo[dd], hi[dd]);
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) EB[pidx(G, c, i, j, k)] = out[pidx(G, c, i, j, k)];
+  }
+  fill_periodic_ghosts(G, EB, 3);
+}
+
+// One pass of the digital filter of Sec. 2.5 on the conformal current: each
+// component on its own lattice, weights (1/2)^(D + |di| + |dj| + |dk|) over
+// the 3^D neighbourhood.  Periodic Cartesian grids wrap; (quasi-)spherical
+// grids mirror across the axes (Sec. 2.6: J1(j = -1) = J1(j = +1),
+// J2(j = -1/2) = -J2(j = +1/2), J3 = 0 on the axis, and likewise at
+// theta = pi) and read the stored ghost values across the radial edges
+// (filtered: the updated node ranges of the solver; ghosts unchanged).
+double j_at(const Grid &G, const double *J, int c, int i, int j, int k) {
+  if (G.geom == 0) {
+    int ii[3] = {i, j, k};
+    for (int dd = 0; dd < G.dim; ++dd) {
+      ii[dd] %= G.n[dd];
+      if (ii[dd] < 0) ii[dd] += G.n[dd];
+    }
+    return J[pidx(G, c, ii[0], ii[1], ii[2])];
+  }
+  const int n2 = G.n[1];
+  if (c == 2 && (j == 0 || j == n2)) return 0.0;
+  if (c == 1) {  // half-integer points j + 1/2
+    if (j < 0) return -J[pidx(G, c, i, -1 - j, k)];
+    if (j >= n2) return -J[pidx(G, c, i, 2 * n2 - 1 - j, k)];
+  } else {  // integer nodes
+    if (j < 0) return J[pidx(G, c, i, -j, k)];
+    if (j > n2) return J[pidx(G, c, i, 2 * n2 - j, k)];
+  }
+  return J[pidx(G, c, i, j, k)];
+}
+
+void filter_pass(const Grid &G, double *J) {
+  std::vector<double> out(J, J + 3 * G.npts);
+  const int D = G.dim;
+  for (int c = 0; c < 3; ++c) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) node_range(G, dd, STAG[c][dd], lo[dd], hi[dd]);
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) {
+          double acc = 0.0;
+          const int kr = (D == 3) ? 1 : 0;
+          for (int dk = -kr; dk <= kr; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+              for (int di = -1; di <= 1; ++di) {
+                const int e = D + std::abs(di) + std::abs(dj) + std::abs(dk);
+                acc += std::ldexp(1.0, -e) * j_at(G, J, c, i + di, j + dj, k + dk);
+              }
+          out[pidx(G, c, i, j, k)] = (c == 2 && on_axis(G, j)) ? 0.0 : acc;
+        }
+  }
+  std::copy(out.begin(), out.end(), J);
+}
+
 }  // namespace
 
 // ============================================================== extern "C"
@@ -992,6 +1197,31 @@ void orc_vay(int64_t n, double k, const double *E3, const double *B3, double *u3
 
 void orc_gca(int64_t n, double k, const double *E3, const double *B3, double *u3) {
   for (int64_t p = 0; p < n; ++p) gca_push(k, E3 + 3 * p, B3 + 3 * p, u3 + 3 * p);
+}
+
+// field solver pieces on the padded arrays (see the field solver section)
+int orc_faraday(const orc_grid *g, double *EB, double f) {
+  Grid G;
+  if (!make_grid(g, G)) return 1;
+  faraday(G, EB, f);
+  return 0;
+}
+int orc_ampere(const orc_grid *g, double *EB, const double *J, double dt, double coupling) {
+  Grid G;
+  if (!make_grid(g, G)) return 1;
+  ampere(G, EB, J, dt, coupling);
+  return 0;
+}
+int orc_filter(const orc_grid *g, double *J, int32_t passes) {
+  Grid G;
+  if (!make_grid(g, G)) return 1;
+  for (int p = 0; p < passes; ++p) filter_pass(G, J);
+  return 0;
+}
+double orc_polar_area(const orc_grid *g, double x1) {
+  Grid G;
+  if (!make_grid(g, G) || G.geom == 0) return 0.0;
+  return polar_area(G, x1);
 }
 
 void orc_sort_perm(int64_t n, const int32_t *keys, int32_t *perm) {

@@ -77,6 +77,13 @@ int orc_sort_keys(const orc_grid *g, int64_t n, const int32_t *cell, const int32
 int orc_run(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every,
             int64_t step0, const double *EB, int32_t nspecies, const double *q,
             const double *m, orc_species *sp, double *J);
+/* field solver (Sec. 2.3 steps 2, 9-11; App. A; Sec. 2.5, 2.6), in place on
+ * padded arrays: Faraday B -= f curl E / sqrt(h); Ampere E += dt curl B /
+ * sqrt(h) - coupling dt J / sqrt(h) with the axis rules; filter passes */
+int orc_faraday(const orc_grid *g, double *EB, double f);
+int orc_ampere(const orc_grid *g, double *EB, const double *J, double dt, double coupling);
+int orc_filter(const orc_grid *g, double *J, int32_t passes);
+double orc_polar_area(const orc_grid *g, double x1);
 int orc_run_pushers(const orc_grid *g, double dt, int32_t nsteps, int32_t sort_every,
                     int64_t step0, const double *EB, int32_t nspecies, const double *q,
                     const double *m, const int32_t *pusher, const double *e_ovr,

@@ -50,6 +50,7 @@ def lib():
         _LIB.orc_theta_of_T.restype = C.c_double
         _LIB.orc_T_of_theta.restype = C.c_double
         _LIB.orc_field_points.restype = C.c_int64
+        _LIB.orc_polar_area.restype = C.c_double
     return _LIB
 
 
@@ -225,6 +226,38 @@ def sort_keys(g, cell, alive):
     if rc != 0:
         raise RuntimeError(f"orc_sort_keys failed rc={rc}")
     return keys
+
+
+def faraday(g, EB, f):
+    """B -= f curl E / sqrt(h) on a copy of the padded fields (App. A)."""
+    out = np.array(EB, dtype=np.float64, copy=True, order="C")
+    rc = lib().orc_faraday(C.byref(g), _p(out, C.c_double), C.c_double(f))
+    if rc:
+        raise RuntimeError("orc_faraday")
+    return out
+
+
+def ampere(g, EB, J, dt, coupling):
+    """E += dt curl B / sqrt(h) - coupling dt J / sqrt(h), with the axis rules."""
+    out = np.array(EB, dtype=np.float64, copy=True, order="C")
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    rc = lib().orc_ampere(C.byref(g), _p(out, C.c_double), _p(J, C.c_double), C.c_double(dt),
+                          C.c_double(coupling))
+    if rc:
+        raise RuntimeError("orc_ampere")
+    return out
+
+
+def filter_current(g, J, passes=1):
+    out = np.array(J, dtype=np.float64, copy=True, order="C")
+    rc = lib().orc_filter(C.byref(g), _p(out, C.c_double), C.c_int32(passes))
+    if rc:
+        raise RuntimeError("orc_filter")
+    return out
+
+
+def polar_area(g, x1):
+    return lib().orc_polar_area(C.byref(g), C.c_double(x1))
 
 
 def _species_struct(g, st, with_prev=False):
