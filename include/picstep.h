@@ -232,6 +232,20 @@ pic_status pic_particles_load(pic_ctx *ctx, int32_t species, uint64_t n, const i
  * ties keep their order.  Asynchronous. */
 pic_status pic_sort(pic_ctx *ctx);
 
+/* pic_sort without any device allocation by anyone: for callers that cannot
+ * allocate device memory at the time of the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same
+ * result as pic_sort (the permutation is stored in the bound scratch buffer
+ * as usual), but the radix sort's temporaries (keys, values, tile histograms,
+ * column sums) live in a static device array of the library, 66 MiB per GPU,
+ * held until the process ends; no hipMalloc, hipFree or allocating routine is
+ * called.  Limit: at most 4,194,304 (2^22) particles per species, else
+ * PIC_E_CAPACITY before any device work.  The device current at the call must
+ * be the one the context's buffers live on.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU (several streams or host
+ * threads) race.  Asynchronous. */
+pic_status pic_sort_static(pic_ctx *ctx);
+
 /* n_steps particle steps with static fields and step size dt.  Before each
  * step whose global index is a multiple of sort_every (> 0) the particles are
  * sorted.  J is zeroed at the start of every step; after the call it holds

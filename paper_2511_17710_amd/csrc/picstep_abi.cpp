@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -182,17 +183,23 @@ void ev_end(pic_ctx *c, int idx) {
 // into the other set); else the permutation stays pending and the next step
 // reads through it while it writes the sorted, advanced particles into the
 // other set (one pass over the particle data instead of two).
+// tmp: the radix sort's temporaries (keys, values, tile histograms, column
+// sums) from elsewhere than the bound scratch buffer (no timing events then).
 template <class Real>
-pic_status do_sort(pic_ctx *c, bool materialize) {
-  const int ev = ev_begin(c, 1);
+pic_status do_sort(pic_ctx *c, bool materialize, const SortScratch *tmp = nullptr) {
+  const int ev = tmp ? -1 : ev_begin(c, 1);
   SortScratch S{};
-  for (int a = 0; a < 2; ++a) {
-    S.keys[a] = reinterpret_cast<uint32_t *>(c->scratch + c->s_keys[a]);
-    S.vals[a] = reinterpret_cast<int32_t *>(c->scratch + c->s_vals[a]);
+  if (tmp) {
+    S = *tmp;
+  } else {
+    for (int a = 0; a < 2; ++a) {
+      S.keys[a] = reinterpret_cast<uint32_t *>(c->scratch + c->s_keys[a]);
+      S.vals[a] = reinterpret_cast<int32_t *>(c->scratch + c->s_vals[a]);
+    }
+    S.hist = reinterpret_cast<int32_t *>(c->scratch + c->s_hist);
+    S.bsum = reinterpret_cast<int32_t *>(c->scratch + c->s_bsum);
+    S.max_tiles = c->max_tiles;
   }
-  S.hist = reinterpret_cast<int32_t *>(c->scratch + c->s_hist);
-  S.bsum = reinterpret_cast<int32_t *>(c->scratch + c->s_bsum);
-  S.max_tiles = c->max_tiles;
   int32_t *perm = reinterpret_cast<int32_t *>(c->scratch + c->s_perm);
   PSet<Real> src = pset_of<Real>(c, c->active), dst = pset_of<Real>(c, c->active ^ 1);
   for (int s = 0; s < c->nspec; ++s) {
@@ -966,6 +973,69 @@ pic_status pic_sort(pic_ctx *c) {
   pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;
   return c->eb == 8 ? do_sort<double>(c, true) : do_sort<float>(c, true);
+}
+
+// ---- the allocation-free sort: the radix temporaries live in a static
+// device array (one per GPU, held until the process ends) instead of the
+// caller's scratch buffer.
+namespace {
+constexpr int64_t STATIC_SORT_MAX = int64_t(1) << 22;  // particles per species
+constexpr int64_t STATIC_SORT_TILES = STATIC_SORT_MAX / SORT_TILE;
+constexpr uint64_t SS_ARRAY = (uint64_t)STATIC_SORT_MAX * 4;  // one key or value array
+constexpr uint64_t SS_HIST = (uint64_t)STATIC_SORT_TILES * 256 * 4;
+constexpr uint64_t SS_BSUM = (uint64_t)SCAN_CHUNKS * 256 * 4;
+constexpr uint64_t SS_BYTES = 4 * SS_ARRAY + SS_HIST + SS_BSUM;
+static_assert(SS_ARRAY % ALIGN == 0 && SS_HIST % ALIGN == 0, "static scratch alignment");
+constexpr int SS_MAX_DEVICES = 64;
+std::mutex ss_mutex;
+char *ss_ptr[SS_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SS_BYTES];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the array's host-side name is not a device
+// address and is never passed to a kernel or copy).
+static pic_status static_scratch(pic_ctx *c, char **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hipchk(c, e, "hipGetDevice");
+  if (dev < 0 || dev >= SS_MAX_DEVICES) return fail(c, PIC_E_UNSUPPORTED, "device %d", dev);
+  std::lock_guard<std::mutex> lock(ss_mutex);
+  if (!ss_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hipchk(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(c, PIC_E_HIP, "hipGetSymbolAddress(scratch) returned null");
+    ss_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = ss_ptr[dev];
+  return PIC_OK;
+}
+
+pic_status pic_sort_static(pic_ctx *c) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "sort before bind_buffers");
+  for (int s = 0; s < c->nspec; ++s)
+    if ((int64_t)c->cnt[s] > STATIC_SORT_MAX)
+      return fail(c, PIC_E_CAPACITY,
+                  "species %d holds %llu particles; the allocation-free sort takes at most %lld "
+                  "per species (use pic_sort)",
+                  s, (unsigned long long)c->cnt[s], (long long)STATIC_SORT_MAX);
+  char *base = nullptr;
+  pic_status st = static_scratch(c, &base);
+  if (st != PIC_OK) return st;
+  SortScratch S{};
+  S.keys[0] = reinterpret_cast<uint32_t *>(base);
+  S.vals[0] = reinterpret_cast<int32_t *>(base + SS_ARRAY);
+  S.keys[1] = reinterpret_cast<uint32_t *>(base + 2 * SS_ARRAY);
+  S.vals[1] = reinterpret_cast<int32_t *>(base + 3 * SS_ARRAY);
+  S.hist = reinterpret_cast<int32_t *>(base + 4 * SS_ARRAY);
+  S.bsum = reinterpret_cast<int32_t *>(base + 4 * SS_ARRAY + SS_HIST);
+  S.max_tiles = STATIC_SORT_TILES;
+  st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
+  return c->eb == 8 ? do_sort<double>(c, true, &S) : do_sort<float>(c, true, &S);
 }
 
 pic_status pic_push_deposit(pic_ctx *c, double dt, int32_t n_steps) {

@@ -94,6 +94,7 @@ def lib():
             "pic_fields_fill_ghosts": [vp],
             "pic_particles_load": [vp, i32, u64, vp, vp, vp, vp, vp],
             "pic_sort": [vp],
+            "pic_sort_static": [vp],
             "pic_push_deposit": [vp, dbl, i32],
             "pic_current_get": [vp, vp, i32],
             "pic_fields_get": [vp, vp, i32],
@@ -258,6 +259,11 @@ class Context:
     # -------------------------------------------------------------- the step
     def sort(self):
         self._check(lib().pic_sort(self.h), "sort")
+
+    def sort_static(self):
+        """pic_sort with the radix temporaries in the library's static device
+        array (no allocation; at most 2^22 particles per species)."""
+        self._check(lib().pic_sort_static(self.h), "sort_static")
 
     def push_deposit(self, dt, n_steps):
         self._check(lib().pic_push_deposit(self.h, float(dt), int(n_steps)), "push_deposit")
