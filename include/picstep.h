@@ -256,6 +256,48 @@ pic_status pic_sort_static(pic_ctx *ctx);
  * and is then dead.  Asynchronous. */
 pic_status pic_push_deposit(pic_ctx *ctx, double dt, int32_t n_steps);
 
+/* ---- field solver: the field update around the particle step (Sec. 2.3
+ * steps 2, 9-11), in place on the bound field buffer, in the discretized
+ * forms of App. A: covariant components F_i = h_ii F^i differenced over unit
+ * code cells and divided by sqrt(h) = sqrt(h11 h22 h33) at the updated
+ * component's Yee point; metric factors are computed on the fly in FP64.
+ * Updated points: periodic Cartesian grids the active region (ghosts
+ * refilled from their images); (quasi-)spherical grids the nodes 0..N
+ * (integer-staggered components) or cells 0..N-1 (half-staggered) of each
+ * dimension, the radial ghosts being the caller's boundary values.  On the
+ * polar axis (j = 0 and j = N2) E3 and B2 are kept 0 and E1 takes the
+ * update integrated over the half cell next to the axis (Sec. 2.6).  All
+ * asynchronous; PIC_E_ARG for a step above the CFL limit. */
+
+/* Faraday (eq. discretized-faraday): B^i -= f (curl E)^i / sqrt(h).  The loop
+ * takes two half steps, f = dt / 2, around the particle step. */
+pic_status pic_fields_advance_b(pic_ctx *ctx, double f);
+
+/* Ampere (eq. discretized-ampere) with the bound current buffer (the
+ * conformal current of the last particle step): E^i += dt ((curl B)^i -
+ * coupling J^i) / sqrt(h).  coupling is the factor the method writes as 4 pi
+ * (with fields in units of B0, lengths of rho0 and the macro-particle
+ * weights of the current, the plasma frequency of a cold species of
+ * charge q, mass m and weight per unit volume n is sqrt(coupling n q^2 / m)). */
+pic_status pic_fields_advance_e(pic_ctx *ctx, double dt, double coupling);
+
+/* passes of the digital filter of Sec. 2.5 on the bound current buffer:
+ * each component on its own lattice, weights (1/2)^(D + |di| + |dj| + |dk|)
+ * over its 3^D neighbours; periodic Cartesian grids wrap, (quasi-)spherical
+ * grids mirror across the axes (J1 even, J2 odd, J3 zero on the axis,
+ * Sec. 2.6) and read the stored radial ghosts.  work: device buffer of
+ * current_bytes (caller-owned scratch). */
+pic_status pic_current_filter(pic_ctx *ctx, int32_t passes, void *work);
+
+/* n_steps of the whole loop of Sec. 2.3: Faraday dt/2; the particle step
+ * (sort at the context's cadence, interpolation at B^n, E^n, push, deposit);
+ * filter_passes of the current filter; Faraday dt/2; Ampere with the filtered
+ * current.  work as for pic_current_filter (may be NULL without passes).
+ * After the call the bound buffers hold B^{n+1/2}, E^{n+1}, the particles at
+ * x^{n+1}, u^{n+1/2}, and the (filtered) current of the last step. */
+pic_status pic_step_full(pic_ctx *ctx, double dt, int32_t n_steps, int32_t filter_passes,
+                         double coupling, void *work);
+
 /* Copies the current [3][npts] (storage precision) to dst, on the device
  * (dst_is_device = 1, asynchronous) or the host (synchronizes). */
 pic_status pic_current_get(const pic_ctx *ctx, void *dst, int32_t dst_is_device);

@@ -115,6 +115,14 @@ template <class Real>
 hipError_t launch_fold_ghosts(const GridConst &g, Real *A, int ncomp, hipStream_t s);
 template <class Real>
 hipError_t launch_zero(Real *A, int64_t n, hipStream_t s);
+// field solver (k_fields.hip)
+template <class Real>
+hipError_t launch_faraday(const GridConst &g, Real *EB, double f, hipStream_t s);
+template <class Real>
+hipError_t launch_ampere(const GridConst &g, Real *EB, const Real *J, double dt, double coupling,
+                         hipStream_t s);
+template <class Real>
+hipError_t launch_filter(const GridConst &g, const Real *in, Real *out, hipStream_t s);
 
 // stable sort of one species range by cell key; writes perm (new i <- old perm[i])
 struct SortScratch {

@@ -1049,6 +1049,90 @@ pic_status pic_push_deposit(pic_ctx *c, double dt, int32_t n_steps) {
   return c->eb == 8 ? run_steps<double>(c, dt, n_steps, true) : run_steps<float>(c, dt, n_steps, true);
 }
 
+}  // extern "C"
+
+// ---- field solver and the full loop (Sec. 2.3 steps 2, 9-11; App. A; Sec. 2.5, 2.6)
+namespace {
+template <class Real>
+pic_status advance_b(pic_ctx *c, double f) {
+  return hipchk(c, launch_faraday<Real>(c->g, reinterpret_cast<Real *>(c->fields), f, c->stream),
+                "faraday");
+}
+template <class Real>
+pic_status advance_e(pic_ctx *c, double dt, double coupling) {
+  return hipchk(c,
+                launch_ampere<Real>(c->g, reinterpret_cast<Real *>(c->fields),
+                                    reinterpret_cast<const Real *>(c->current), dt, coupling,
+                                    c->stream),
+                "ampere");
+}
+// passes of the filter, ping-ponging between the current and `work`; an odd
+// count ends with a copy back
+template <class Real>
+pic_status filter_current(pic_ctx *c, int32_t passes, void *work) {
+  Real *J = reinterpret_cast<Real *>(c->current), *W = static_cast<Real *>(work);
+  hipError_t e = hipSuccess;
+  for (int32_t p = 0; p < passes && e == hipSuccess; ++p) {
+    e = launch_filter<Real>(c->g, J, W, c->stream);
+    std::swap(J, W);
+  }
+  if (e == hipSuccess && (passes & 1))
+    e = hipMemcpyAsync(c->current, J, 3ull * c->g.npts * sizeof(Real), hipMemcpyDeviceToDevice,
+                       c->stream);
+  return hipchk(c, e, "filter");
+}
+template <class Real>
+pic_status full_steps(pic_ctx *c, double dt, int32_t n, int32_t passes, double coupling,
+                      void *work) {
+  for (int32_t s = 0; s < n; ++s) {
+    pic_status st = advance_b<Real>(c, 0.5 * dt);
+    if (st == PIC_OK) st = run_steps<Real>(c, dt, 1, true);
+    if (st == PIC_OK && passes > 0) st = filter_current<Real>(c, passes, work);
+    if (st == PIC_OK) st = advance_b<Real>(c, 0.5 * dt);
+    if (st == PIC_OK) st = advance_e<Real>(c, dt, coupling);
+    if (st != PIC_OK) return st;
+  }
+  return PIC_OK;
+}
+bool field_dt_ok(pic_ctx *c, double dt) {
+  return dt > 0 && isfin(dt) && dt <= c->dx_min;
+}
+}  // namespace
+
+extern "C" {
+
+pic_status pic_fields_advance_b(pic_ctx *c, double f) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "faraday before bind/fields_set");
+  if (!isfin(f) || std::fabs(f) > c->dx_min) return fail(c, PIC_E_ARG, "bad faraday step %g", f);
+  return c->eb == 8 ? advance_b<double>(c, f) : advance_b<float>(c, f);
+}
+
+pic_status pic_fields_advance_e(pic_ctx *c, double dt, double coupling) {
+  if (!c) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "ampere before bind/fields_set");
+  if (!field_dt_ok(c, dt) || !isfin(coupling)) return fail(c, PIC_E_ARG, "bad dt or coupling");
+  return c->eb == 8 ? advance_e<double>(c, dt, coupling) : advance_e<float>(c, dt, coupling);
+}
+
+pic_status pic_current_filter(pic_ctx *c, int32_t passes, void *work) {
+  if (!c || passes < 0 || (passes > 0 && !work)) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "filter before bind_buffers");
+  return c->eb == 8 ? filter_current<double>(c, passes, work)
+                    : filter_current<float>(c, passes, work);
+}
+
+pic_status pic_step_full(pic_ctx *c, double dt, int32_t n_steps, int32_t filter_passes,
+                         double coupling, void *work) {
+  if (!c || n_steps < 0 || filter_passes < 0 || (filter_passes > 0 && !work)) return PIC_E_ARG;
+  if (!c->bound || !c->fields_ok) return fail(c, PIC_E_STATE, "step before bind/fields_set");
+  if (!field_dt_ok(c, dt) || !isfin(coupling)) return fail(c, PIC_E_ARG, "bad dt or coupling");
+  const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
+  if (st != PIC_OK) return st;
+  return c->eb == 8 ? full_steps<double>(c, dt, n_steps, filter_passes, coupling, work)
+                    : full_steps<float>(c, dt, n_steps, filter_passes, coupling, work);
+}
+
 pic_status pic_current_get(const pic_ctx *c, void *dst, int32_t dst_is_device) {
   if (!c || !dst) return PIC_E_ARG;
   if (!c->bound) return fail(c, PIC_E_STATE, "not bound");

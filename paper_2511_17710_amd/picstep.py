@@ -96,6 +96,10 @@ def lib():
             "pic_sort": [vp],
             "pic_sort_static": [vp],
             "pic_push_deposit": [vp, dbl, i32],
+            "pic_fields_advance_b": [vp, dbl],
+            "pic_fields_advance_e": [vp, dbl, dbl],
+            "pic_current_filter": [vp, i32, vp],
+            "pic_step_full": [vp, dbl, i32, i32, dbl, vp],
             "pic_current_get": [vp, vp, i32],
             "pic_fields_get": [vp, vp, i32],
             "pic_particles_get": [vp, i32, C.POINTER(ParticleView)],
@@ -267,6 +271,33 @@ class Context:
 
     def push_deposit(self, dt, n_steps):
         self._check(lib().pic_push_deposit(self.h, float(dt), int(n_steps)), "push_deposit")
+
+    # -------------------------------------------------------------- field solver
+    def _work(self):
+        w = getattr(self, "_jwork", None)
+        if w is None:
+            w = torch.empty(max(int(self.sizes().current_bytes), 256), dtype=torch.uint8,
+                            device=self.device)
+            self._jwork = w
+        return C.c_void_p(w.data_ptr())
+
+    def fields_advance_b(self, f):
+        """Faraday: B -= f curl E / sqrt(h)."""
+        self._check(lib().pic_fields_advance_b(self.h, float(f)), "fields_advance_b")
+
+    def fields_advance_e(self, dt, coupling=4 * np.pi):
+        """Ampere with the bound current: E += dt (curl B - coupling J) / sqrt(h)."""
+        self._check(lib().pic_fields_advance_e(self.h, float(dt), float(coupling)),
+                    "fields_advance_e")
+
+    def current_filter(self, passes):
+        self._check(lib().pic_current_filter(self.h, int(passes), self._work()), "current_filter")
+
+    def step_full(self, dt, n_steps, filter_passes=0, coupling=4 * np.pi):
+        """n_steps of the whole loop (fields evolved with the particles)."""
+        w = self._work() if filter_passes > 0 else None
+        self._check(lib().pic_step_full(self.h, float(dt), int(n_steps), int(filter_passes),
+                                        float(coupling), w), "step_full")
 
     def step_count(self):
         v = C.c_int64()

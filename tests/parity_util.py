@@ -1,5 +1,7 @@
 """Runs one workload through the FP64 reference and through the HIP library
 from the same seeded inputs, and measures their agreement."""
+import copy
+
 import numpy as np
 
 from oracle import oracle as O
@@ -86,3 +88,15 @@ def continuity_of(wl, J, species, dt):
 
 def near_face(offs, tol):
     return np.any((offs < tol) | (offs > 1 - tol), axis=1)
+
+
+_WL_CACHE = {}
+
+
+def cached_workload(name):
+    """A deep copy of a full-size workload, generated once while consecutive
+    tests ask for the same one (one kept at a time: they are large)."""
+    if name not in _WL_CACHE:
+        _WL_CACHE.clear()
+        _WL_CACHE[name] = W.by_name(name)
+    return copy.deepcopy(_WL_CACHE[name])

@@ -17,8 +17,6 @@ so every check uses outputs it can compute piecewise:
   depends only on that particle's trajectory, so sampled particles are
   compared with the reference adjoint of those particles alone.
 """
-import copy
-
 import numpy as np
 import pytest
 
@@ -29,15 +27,9 @@ from tests import parity_util as U
 
 pytestmark = pytest.mark.gpu
 
-_CACHE = {}
-
-
 def _workload(name):
-    if name not in _CACHE:
-        _CACHE.clear()
-        print(f"[fullsize] generating {name}", flush=True)
-        _CACHE[name] = W.by_name(name)
-    return copy.deepcopy(_CACHE[name])
+    print(f"[fullsize] {name}", flush=True)
+    return U.cached_workload(name)
 
 
 def _subset(species, idx):

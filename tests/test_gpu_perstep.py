@@ -143,7 +143,7 @@ def _run_case(name, prec, checkpoints, boxes, whole, nsample, cold_first=False):
 
     from paper_2511_17710_amd import picstep as P
     print(f"[perstep] {name} {prec}: generating", flush=True)
-    wl = W.by_name(name)
+    wl = U.cached_workload(name)
     if prec == "f32":
         W.round_to_f32(wl)
     g, EB = U.oracle_fields(wl, prec)
