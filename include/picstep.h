@@ -229,7 +229,13 @@ pic_status pic_particles_load(pic_ctx *ctx, int32_t species, uint64_t n, const i
                               const double *phi);
 
 /* Stable per-cell counting sort of every species (dead particles last);
- * ties keep their order.  Asynchronous. */
+ * ties keep their order.  Cells are ordered brick by brick (4x4x4 in 3D,
+ * 8x8 in 2D).  When the particles are still in the order of the previous
+ * sort and the library's own steps since then cannot have moved any of them
+ * by more than one brick per dimension, the sort takes the brick-neighbour
+ * form (counts per neighbouring brick, then a counting sort inside each
+ * brick); otherwise three radix passes.  Same permutation either way.
+ * Asynchronous. */
 pic_status pic_sort(pic_ctx *ctx);
 
 /* pic_sort without any device allocation by anyone: for callers that cannot
@@ -330,6 +336,8 @@ typedef struct {
   int64_t push_blocks;           /* blocks of the fused kernel with live particles */
   int64_t push_global_particles; /* particles whose stencil left the LDS tile, deposited with
                                     global atomics */
+  int64_t sort_brick_calls;      /* sorts that took the brick-neighbour form (counted whether
+                                    or not timing is enabled) */
 } pic_timing;
 pic_status pic_timing_enable(pic_ctx *ctx, int32_t enable);
 pic_status pic_timing_read(pic_ctx *ctx, pic_timing *out);
@@ -405,6 +413,28 @@ typedef struct {
  * are none).  The particle state is left unchanged.  Asynchronous. */
 pic_status pic_adjoint_step(pic_ctx *ctx, double dt, const void *lamJ,
                             const pic_adjoint_buffers *io);
+
+/* ---- failure detection ----
+ * The kernels raise bits of a sticky device error word instead of trapping:
+ *   PIC_DEVERR_NONFINITE  a push produced a non-finite four-velocity (NaN or
+ *                         infinite fields, momenta or weights); the particle
+ *                         is kept as computed;
+ *   PIC_DEVERR_SORT_MOVE  at a sort, a particle had crossed more than one
+ *                         brick of the sort order in some dimension since the
+ *                         previous sort (its cell was changed through the
+ *                         bound buffers without pic_particles_modified); that
+ *                         sort kept the previous order (identity permutation).
+ * pic_device_errors waits for the bound stream, returns the word in *flags
+ * and, when clear != 0, clears it. */
+#define PIC_DEVERR_NONFINITE 1
+#define PIC_DEVERR_SORT_MOVE 2
+pic_status pic_device_errors(pic_ctx *ctx, int32_t *flags, int32_t clear);
+
+/* Tells the library that the particle arrays were written through the bound
+ * buffers (not by its own calls): the next sort then makes no assumption
+ * about how far particles moved since the previous one (Sec. 3.3.2 sort of
+ * the particle arrays; the fast form assumes moves of at most one brick). */
+pic_status pic_particles_modified(pic_ctx *ctx);
 
 /* Message of the last failing call on this context (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);

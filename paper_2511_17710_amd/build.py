@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpicstep.so")
-SOURCES = ["k_push.hip", "k_sort.hip", "k_util.hip", "k_adjoint.hip", "k_fields.hip",
-           "picstep_abi.cpp"]
+SOURCES = ["k_push.hip", "k_sort.hip", "k_bsort.hip", "k_util.hip", "k_adjoint.hip",
+           "k_fields.hip", "picstep_abi.cpp"]
 FLAGS = ["-O3", "-gline-tables-only", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I" + os.path.join(HERE, "..", "include")]

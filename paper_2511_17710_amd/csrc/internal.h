@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "picstep.h"
+
 namespace picstep {
 
 constexpr int NG = 2;                  // ghost cells per side (Sec. 3.1)
@@ -81,6 +83,7 @@ struct StepArgs {
   int write_prev;
   int deposit;             // 0: move only (adjoint recompute)
   int32_t *stats;          // [0]: blocks, [1]: blocks that deposited with global atomics
+  int32_t *err;            // sticky device error word (PIC_DEVERR_* bits)
   // a sort's pending reorder (perm == nullptr: none): particle i of a species
   // is read from src at the species-local index perm[i], and the step writes
   // the sorted, advanced particles into p
@@ -132,9 +135,41 @@ struct SortScratch {
   int32_t *bsum;      // column sums of tile chunks: SCAN_CHUNKS x 256
   int64_t max_tiles;
 };
+// keys_out (optional): where the sorted keys are left
 hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
                                const SortScratch &S, int32_t *perm_out, int keybits,
-                               hipStream_t s);
+                               hipStream_t s, const uint32_t **keys_out = nullptr);
+// brick starts of a sorted key sequence: bstart[b] = first index of brick b,
+// bstart[nb] = first dead particle, bstart[nb + 1] = n
+hipError_t launch_brick_bounds(const uint32_t *keys, int64_t n, int nb, int localbits,
+                               uint32_t deadkey, int32_t *bstart, hipStream_t s);
+
+// brick-neighbour sort of one species (k_bsort.hip): the species is in the
+// order of its previous sort, whose brick starts are bold, and no particle
+// has since crossed more than one brick in any dimension
+struct BrickSortArgs {
+  GridConst g;
+  int nb;                // bricks
+  int localbits;         // bits of the cell inside a brick (64 cells)
+  uint32_t deadkey;
+  int64_t n;             // particles of the species
+  const int32_t *cell;   // species range, previous order
+  const int32_t *bold;   // nb + 2: previous brick starts (entry nb: the dead), [nb + 1] = n
+  int32_t *bnew;         // nb + 2: the new brick starts
+  int32_t *cnt;          // (nb + 1) x (3^dim + 1): counts per destination, then its start
+  int32_t *tot;          // nb: particles per new brick
+  int32_t *dpre;         // nb + 1: dead particles of each old bin, then the exclusive prefix
+  uint32_t *tkey;        // n: keys in brick-grouped order
+  int32_t *tval;         // n: their previous indices
+  int32_t *perm;         // n: new i <- previous perm[i]
+  int32_t *flag;         // raised when a particle moved beyond the neighbours
+  int32_t *err;          // sticky device error word
+};
+// writes the permutation; move: also moves every particle record from src
+// into dst (species offset off)
+template <class Real>
+hipError_t launch_brick_sort(const BrickSortArgs &a, const PSet<Real> &src, const PSet<Real> &dst,
+                             int64_t off, int has_phi, bool move, hipStream_t s);
 template <class Real>
 hipError_t launch_gather(const PSet<Real> &src, const PSet<Real> &dst, int dim, int has_phi,
                          int64_t off, int64_t n, const int32_t *perm, hipStream_t s);

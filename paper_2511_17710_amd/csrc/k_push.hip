@@ -562,6 +562,7 @@ void k_push(StepArgs<Real> A) {
   int mp[PPT];
   Real d3[PPT];
   float bmax = 0.0f;
+  bool nonfinite = false;  // a non-finite four-velocity (reported, not trapped)
   const Real qdt = (Real)A.sp.qdt[s];
   auto push_pass = [&](auto check) {
     constexpr bool CHK = decltype(check)::value;
@@ -591,6 +592,7 @@ void k_push(StepArgs<Real> A) {
       for (int a = 0; a < DIM; ++a) qd[a][r] = q[a];
 #pragma unroll
       for (int a = 0; a < 3; ++a) uu[a][r] = u[a];
+      nonfinite = nonfinite || !(fabs(u[0]) + fabs(u[1]) + fabs(u[2]) < (Real)INFINITY);
       bmax = fmaxf(bmax, fabsf((float)(qdt * ww[r])) * fmaxf(span, fabsf((float)dx3)));
     }
   };
@@ -598,6 +600,7 @@ void k_push(StepArgs<Real> A) {
     push_pass(std::false_type{});
   else
     push_pass(std::true_type{});
+  if (nonfinite && A.err) atomicOr(A.err, PIC_DEVERR_NONFINITE);
 
   store_n(A.p.cell + p0, cnt, cl);
 #pragma unroll

@@ -8,7 +8,7 @@
 // start of every digit of every tile), and a stable in-tile ranking with
 // wave ballots followed by a scatter.  A gather then reorders every SoA array into
 // the second particle set.
-#include "internal.h"
+#include "step_device.h"
 
 namespace picstep {
 
@@ -38,21 +38,6 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh_w
   __syncthreads();
   *total = tot;
   return pre + x - v;
-}
-
-// key of a cell: cells brick by brick (brick index, then the cell inside the
-// brick, x fastest in both), or deadkey = 1 << (keybits - 1) when dead; brick
-// sides are powers of two
-__device__ __forceinline__ uint32_t brick_key(const GridConst &g, int32_t c, uint32_t deadkey) {
-  if (c & DEAD_BIT) return deadkey;
-  const uint32_t ii[3] = {(uint32_t)((c & g.mask1) - 1), (uint32_t)((c >> g.shift2) & g.mask2),
-                          (uint32_t)((c >> g.shift3) & g.mask3)};
-  const int s0 = g.brick_shift[0], s1 = g.brick_shift[1], s2 = g.brick_shift[2];
-  const uint32_t brick = (ii[0] >> s0) + (uint32_t)g.nbrick[0] * ((ii[1] >> s1) +
-                         (uint32_t)g.nbrick[1] * (ii[2] >> s2));
-  const uint32_t local = (ii[0] & ((1u << s0) - 1)) | ((ii[1] & ((1u << s1) - 1)) << s0) |
-                         ((ii[2] & ((1u << s2) - 1)) << (s0 + s1));
-  return (brick << (s0 + s1 + s2)) | local;
 }
 
 // The first radix pass reads the cells and forms key and index on the fly
@@ -265,7 +250,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 
 hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t n,
                                const SortScratch &S, int32_t *perm_out, int keybits,
-                               hipStream_t s) {
+                               hipStream_t s, const uint32_t **keys_out) {
   if (n <= 0) return hipSuccess;
   const int64_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   if (ntiles > S.max_tiles) return hipErrorInvalidValue;
@@ -285,7 +270,9 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
     hipLaunchKernelGGL(k_col_apply, dim3((unsigned)nchunks), dim3(RADIX), 0, s, S.hist, ntiles,
                        ct, S.bsum);
     int32_t *vdst = (ps == passes - 1) ? perm_out : S.vals[dst];
-    uint32_t *kdst = (ps == passes - 1) ? nullptr : S.keys[dst];
+    // the last pass keeps the keys only when the caller wants them
+    uint32_t *kdst = (ps == passes - 1 && !keys_out) ? nullptr : S.keys[dst];
+    if (ps == passes - 1 && keys_out) *keys_out = S.keys[dst];
     if (ps == 0)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
                          ks, kdst, vdst, n, shift, S.hist, ntiles);
@@ -293,6 +280,30 @@ hipError_t launch_sort_species(const GridConst &g, const int32_t *cell, int64_t 
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntiles), dim3(SORT_THREADS), 0, s,
                          ks, kdst, vdst, n, shift, S.hist, ntiles);
   }
+  return hipGetLastError();
+}
+
+// Brick starts of sorted keys: index i opens every bin in (bin(i-1), bin(i)]
+// (bin = brick, or nb for the dead); i = n closes the rest.
+__global__ __launch_bounds__(SORT_THREADS) void k_brick_bounds(const uint32_t *__restrict__ keys,
+                                                               int64_t n, int nb, int localbits,
+                                                               uint32_t deadkey,
+                                                               int32_t *__restrict__ bstart) {
+  const int64_t i = (int64_t)blockIdx.x * SORT_THREADS + threadIdx.x;
+  if (i > n) return;
+  auto bin = [&](int64_t j) {
+    const uint32_t k = keys[j];
+    return k == deadkey ? nb : (int)(k >> localbits);
+  };
+  const int lo = (i == 0) ? -1 : bin(i - 1);
+  const int hi = (i == n) ? nb + 1 : bin(i);
+  for (int b = lo + 1; b <= hi; ++b) bstart[b] = (int32_t)i;
+}
+
+hipError_t launch_brick_bounds(const uint32_t *keys, int64_t n, int nb, int localbits,
+                               uint32_t deadkey, int32_t *bstart, hipStream_t s) {
+  hipLaunchKernelGGL(k_brick_bounds, dim3((unsigned)(n / SORT_THREADS + 1)), dim3(SORT_THREADS), 0,
+                     s, keys, n, nb, localbits, deadkey, bstart);
   return hipGetLastError();
 }
 

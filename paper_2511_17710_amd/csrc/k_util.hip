@@ -118,5 +118,6 @@ template hipError_t launch_fold_ghosts<float>(const GridConst &, float *, int, h
 template hipError_t launch_fold_ghosts<double>(const GridConst &, double *, int, hipStream_t);
 template hipError_t launch_zero<float>(float *, int64_t, hipStream_t);
 template hipError_t launch_zero<double>(double *, int64_t, hipStream_t);
+template hipError_t launch_zero<int32_t>(int32_t *, int64_t, hipStream_t);
 
 }  // namespace picstep

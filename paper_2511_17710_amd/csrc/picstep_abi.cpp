@@ -63,6 +63,16 @@ struct pic_ctx {
   int64_t ckpt_step0 = 0;
   std::vector<int32_t> ckpt_sorts;  // steps n of that run that began with a sort
   bool perm_pending = false;        // a sort's reorder left to the next step
+  // brick-neighbour sort: brick starts of the last sort per species (two
+  // arrays each, bsel the current one), whether they describe the present
+  // order, and a bound on the cells any particle can have moved since
+  uint64_t s_bstart = 0, s_bcnt = 0, s_btot = 0, s_bdpre = 0, s_err = 0;
+  int nbricks = 0, brick_min = 0;
+  int bsel[MAXSP]{};
+  bool bricks_valid = false;
+  int64_t brick_sorts = 0;  // sorts that took the brick-neighbour form
+  double moved = 0.0;
+  double max_inv_dx = 0.0;  // Cartesian: largest 1 / dx
   bool timing = false;
   struct Ev {
     hipEvent_t a, b;
@@ -179,10 +189,39 @@ void ev_end(pic_ctx *c, int idx) {
   if (idx >= 0) (void)hipEventRecord(c->events[idx].b, c->stream);
 }
 
-// The stable per-cell sort.  materialize: reorder every array now (gather
-// into the other set); else the permutation stays pending and the next step
-// reads through it while it writes the sorted, advanced particles into the
-// other set (one pass over the particle data instead of two).
+int32_t *bstart_of(pic_ctx *c, int s, int which) {
+  return reinterpret_cast<int32_t *>(c->scratch + c->s_bstart) +
+         (int64_t)(2 * s + which) * (c->nbricks + 2);
+}
+int32_t *err_word(pic_ctx *c) { return reinterpret_cast<int32_t *>(c->scratch + c->s_err); }
+
+// cells a particle can cross in one step of size dt and dimension: below
+// dt / dx on a Cartesian grid (|v| < c = 1); at most one on any grid (the
+// move clamps its cell step to -1 ... 1)
+double step_cells(const pic_ctx *c, double dt) {
+  if (c->g.geom == 0) return std::min(1.0, dt * c->max_inv_dx * (1.0 + 1e-6));
+  return 1.0;
+}
+
+// The brick-neighbour form applies when the present order is that of the
+// previous sort (with its brick starts kept) and no particle can have
+// crossed more than one brick in any dimension since: a move of at most
+// brick_min cells changes the brick index by at most one.  Periodic
+// dimensions need at least 3 bricks (so that the neighbours are distinct).
+bool brick_sort_ok(const pic_ctx *c) {
+  if (!c->bricks_valid || c->perm_pending || c->moved > c->brick_min) return false;
+  if (c->g.geom == 0)
+    for (int a = 0; a < c->g.dim; ++a)
+      if (c->g.nbrick[a] < 3) return false;
+  return true;
+}
+
+// The stable per-cell sort: the brick-neighbour form when brick_sort_ok,
+// else the radix sort.  materialize: reorder every array now (into the other
+// set); else the permutation stays pending and the next step reads through
+// it while it writes the sorted, advanced particles into the other set (one
+// pass over the particle data instead of two).  Either way the brick starts
+// of the new order are kept for the next sort.
 // tmp: the radix sort's temporaries (keys, values, tile histograms, column
 // sums) from elsewhere than the bound scratch buffer (no timing events then).
 template <class Real>
@@ -202,15 +241,51 @@ pic_status do_sort(pic_ctx *c, bool materialize, const SortScratch *tmp = nullpt
   }
   int32_t *perm = reinterpret_cast<int32_t *>(c->scratch + c->s_perm);
   PSet<Real> src = pset_of<Real>(c, c->active), dst = pset_of<Real>(c, c->active ^ 1);
+  const uint32_t deadkey = 1u << (c->keybits - 1);
+  const int localbits = c->g.brick_shift[0] + c->g.brick_shift[1] + c->g.brick_shift[2];
+  const bool fast = brick_sort_ok(c);
   for (int s = 0; s < c->nspec; ++s) {
     const int64_t n = (int64_t)c->cnt[s];
     const int64_t o = (int64_t)c->off[s];
-    if (n == 0) continue;
-    hipError_t e = launch_sort_species(c->g, src.cell + o, n, S, perm + o, c->keybits, c->stream);
-    if (e != hipSuccess) return hipchk(c, e, "sort");
-    if (materialize) {
-      e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o, c->stream);
-      if (e != hipSuccess) return hipchk(c, e, "gather");
+    hipError_t e = hipSuccess;
+    if (fast) {
+      BrickSortArgs a{};
+      a.g = c->g;
+      a.nb = c->nbricks;
+      a.localbits = localbits;
+      a.deadkey = deadkey;
+      a.n = n;
+      a.cell = src.cell + o;
+      a.bold = bstart_of(c, s, c->bsel[s]);
+      a.bnew = bstart_of(c, s, c->bsel[s] ^ 1);
+      a.cnt = reinterpret_cast<int32_t *>(c->scratch + c->s_bcnt);
+      a.tot = reinterpret_cast<int32_t *>(c->scratch + c->s_btot);
+      a.dpre = reinterpret_cast<int32_t *>(c->scratch + c->s_bdpre);
+      a.tkey = S.keys[0];
+      a.tval = S.vals[0];
+      a.perm = perm + o;
+      a.err = err_word(c);
+      a.flag = a.err + 1;
+      e = launch_brick_sort<Real>(a, src, dst, o, c->o_phi != NONE, materialize, c->stream);
+      if (e != hipSuccess) return hipchk(c, e, "brick sort");
+      if (n > 0) c->bsel[s] ^= 1;  // an empty species keeps its (empty) starts
+      continue;
+    }
+    if (n > 0) {
+      const uint32_t *keys = nullptr;
+      e = launch_sort_species(c->g, src.cell + o, n, S, perm + o, c->keybits, c->stream, &keys);
+      if (e != hipSuccess) return hipchk(c, e, "sort");
+      e = launch_brick_bounds(keys, n, c->nbricks, localbits, deadkey, bstart_of(c, s, c->bsel[s]),
+                              c->stream);
+      if (e != hipSuccess) return hipchk(c, e, "brick bounds");
+      if (materialize) {
+        e = launch_gather<Real>(src, dst, c->g.dim, c->o_phi != NONE, o, n, perm + o, c->stream);
+        if (e != hipSuccess) return hipchk(c, e, "gather");
+      }
+    } else {
+      e = launch_brick_bounds(nullptr, 0, c->nbricks, localbits, deadkey,
+                              bstart_of(c, s, c->bsel[s]), c->stream);
+      if (e != hipSuccess) return hipchk(c, e, "brick bounds");
     }
   }
   // species with no particles keep nothing worth copying; flip the set
@@ -218,6 +293,9 @@ pic_status do_sort(pic_ctx *c, bool materialize, const SortScratch *tmp = nullpt
     c->active ^= 1;
   else
     c->perm_pending = true;
+  c->bricks_valid = true;
+  c->moved = 0.0;
+  c->brick_sorts += fast ? 1 : 0;
   ev_end(c, ev);
   return PIC_OK;
 }
@@ -261,6 +339,8 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   a.write_prev = write_prev ? 1 : 0;
   a.deposit = dep ? 1 : 0;
   a.stats = c->timing ? reinterpret_cast<int32_t *>(c->scratch + c->s_stats) : nullptr;
+  a.err = err_word(c);
+  c->moved += step_cells(c, dt);
   hipError_t e = hipSuccess;
   if (dep) e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "zero J");
@@ -652,6 +732,10 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   }
   const int64_t nkeys = (int64_t)g.nbrick[0] * g.nbrick[1] * g.nbrick[2] *
                         g.brick[0] * g.brick[1] * g.brick[2];
+  c->nbricks = g.nbrick[0] * g.nbrick[1] * g.nbrick[2];
+  c->brick_min = g.brick[0];
+  for (int a = 1; a < d.dim; ++a) c->brick_min = std::min(c->brick_min, g.brick[a]);
+  for (int a = 0; a < d.dim; ++a) c->max_inv_dx = std::max(c->max_inv_dx, g.inv_dx[a]);
   if (bits_for(nkeys) > 30) {
     delete c;
     return PIC_E_UNSUPPORTED;
@@ -706,6 +790,20 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
   o += ai;
   c->s_stats = o;
   o += ALIGN;
+  // brick-neighbour sort: two brick-start arrays per species, the counts per
+  // (old brick, destination), the new bricks' totals, the dead prefixes
+  const uint64_t nbk = (uint64_t)c->nbricks;
+  const uint64_t ndest = (d.dim == 3 ? 27 : 9) + 1;
+  c->s_bstart = o;
+  o += align_up(2ull * MAXSP * (nbk + 2) * 4, ALIGN);
+  c->s_bcnt = o;
+  o += align_up((nbk + 1) * ndest * 4, ALIGN);
+  c->s_btot = o;
+  o += align_up((nbk + 1) * 4, ALIGN);
+  c->s_bdpre = o;
+  o += align_up((nbk + 1) * 4, ALIGN);
+  c->s_err = o;  // [0] device error word, [1] the brick sort's flag
+  o += ALIGN;
   c->scratch_bytes = o;
   // checkpoint: cell, offsets, u, w, phi, id
   c->ckpt_bytes = 2 * ai + (uint64_t)d.dim * ab + 4 * ab + (d.geom != PIC_CART ? ab : 0);
@@ -750,6 +848,8 @@ pic_status pic_bind_buffers(pic_ctx *c, const pic_buffers *b) {
   hipError_t e = hipMemsetAsync(c->prev, 0, c->prev_bytes, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->current, 0, 3ull * c->g.npts * c->eb, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->s_perm, 0, c->capacity * 4, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->scratch + c->s_err, 0, ALIGN, c->stream);
+  c->bricks_valid = false;
   return hipchk(c, e, "bind: clear");
 }
 
@@ -964,6 +1064,7 @@ pic_status pic_particles_load(pic_ctx *c, int32_t s, uint64_t n, const int32_t *
   if (e != hipSuccess) return hipchk(c, e, "particles_load");
   c->cnt[s] = n;
   c->loaded = true;
+  c->bricks_valid = false;
   return PIC_OK;
 }
 
@@ -1288,6 +1389,8 @@ pic_status pic_timing_read(pic_ctx *c, pic_timing *out) {
     (void)hipEventDestroy(e.b);
   }
   c->events.clear();
+  out->sort_brick_calls = c->brick_sorts;
+  c->brick_sorts = 0;
   if (err == hipSuccess && c->bound) {
     int32_t st[4] = {0, 0, 0, 0};
     err = hipMemcpyAsync(st, c->scratch + c->s_stats, 16, hipMemcpyDeviceToHost, c->stream);
@@ -1327,6 +1430,7 @@ pic_status pic_backward(pic_ctx *c, double dt, int32_t K, int32_t m, void *ws, c
     return fail(c, PIC_E_STATE, "backward dt %.17g differs from the forward's %.17g", dt, c->ckpt_dt);
   const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;
+  c->bricks_valid = false;  // the sweep restores and replays states
   return c->eb == 8 ? bwd<double>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0)
                     : bwd<float>(c, dt, K, m, static_cast<char *>(ws), lamJ, lam_u, dEB, du0);
 }
@@ -1376,6 +1480,7 @@ pic_status pic_checkpoint_load(pic_ctx *c, const void *slot) {
   hipError_t e = c->eb == 8
       ? copy_state<double>(c, pset_of<double>(c, c->active), slot_pset<double>(c, sl))
       : copy_state<float>(c, pset_of<float>(c, c->active), slot_pset<float>(c, sl));
+  c->bricks_valid = false;
   return hipchk(c, e, "checkpoint_load");
 }
 
@@ -1388,6 +1493,22 @@ pic_status pic_adjoint_step(pic_ctx *c, double dt, const void *lamJ, const pic_a
   const pic_status st = c->eb == 8 ? settle<double>(c) : settle<float>(c);
   if (st != PIC_OK) return st;
   return c->eb == 8 ? adjoint_one<double>(c, dt, lamJ, io) : adjoint_one<float>(c, dt, lamJ, io);
+}
+
+pic_status pic_device_errors(pic_ctx *c, int32_t *flags, int32_t clear) {
+  if (!c || !flags) return PIC_E_ARG;
+  if (!c->bound) return fail(c, PIC_E_STATE, "device_errors before bind_buffers");
+  int32_t *dev = reinterpret_cast<int32_t *>(c->scratch + c->s_err);
+  hipError_t e = hipMemcpyAsync(flags, dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && clear) e = launch_zero<int32_t>(dev, 1, c->stream);
+  return hipchk(c, e, "device_errors");
+}
+
+pic_status pic_particles_modified(pic_ctx *c) {
+  if (!c) return PIC_E_ARG;
+  c->bricks_valid = false;
+  return PIC_OK;
 }
 
 const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }

@@ -43,6 +43,21 @@ __device__ __forceinline__ int32_t cell_encode(const GridConst &g, const int i[3
   return (int32_t)((i[0] + 1) | (i[1] << g.shift2) | (i[2] << g.shift3));
 }
 
+// key of a cell: cells brick by brick (brick index, then the cell inside the
+// brick, x fastest in both), or deadkey = 1 << (keybits - 1) when dead; brick
+// sides are powers of two
+__device__ __forceinline__ uint32_t brick_key(const GridConst &g, int32_t c, uint32_t deadkey) {
+  if (c & DEAD_BIT) return deadkey;
+  const uint32_t ii[3] = {(uint32_t)((c & g.mask1) - 1), (uint32_t)((c >> g.shift2) & g.mask2),
+                          (uint32_t)((c >> g.shift3) & g.mask3)};
+  const int s0 = g.brick_shift[0], s1 = g.brick_shift[1], s2 = g.brick_shift[2];
+  const uint32_t brick = (ii[0] >> s0) + (uint32_t)g.nbrick[0] * ((ii[1] >> s1) +
+                         (uint32_t)g.nbrick[1] * (ii[2] >> s2));
+  const uint32_t local = (ii[0] & ((1u << s0) - 1)) | ((ii[1] & ((1u << s1) - 1)) << s0) |
+                         ((ii[2] & ((1u << s2) - 1)) << (s0 + s1));
+  return (brick << (s0 + s1 + s2)) | local;
+}
+
 // block -> (species, local index): blocks never straddle species
 __device__ __forceinline__ bool locate(const SpeciesTable &sp, int &s, int64_t &local) {
   const int64_t b = blockIdx.x;

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libpicstep.so")
 
 PIC_OK, PIC_E_ARG, PIC_E_RANGE, PIC_E_STATE, PIC_E_HIP, PIC_E_CAPACITY, PIC_E_UNSUPPORTED = range(7)
+PIC_DEVERR_NONFINITE, PIC_DEVERR_SORT_MOVE = 1, 2
 STATUS = {0: "PIC_OK", 1: "PIC_E_ARG", 2: "PIC_E_RANGE", 3: "PIC_E_STATE", 4: "PIC_E_HIP",
           5: "PIC_E_CAPACITY", 6: "PIC_E_UNSUPPORTED"}
 GEOM = {"cart": 0, "sph": 1, "qsph": 2}
@@ -53,7 +54,8 @@ class Layout(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("push_launches", C.c_int64), ("push_ms", C.c_double), ("sort_calls", C.c_int64),
                 ("sort_ms", C.c_double), ("adjoint_launches", C.c_int64), ("adjoint_ms", C.c_double),
-                ("push_blocks", C.c_int64), ("push_global_particles", C.c_int64)]
+                ("push_blocks", C.c_int64), ("push_global_particles", C.c_int64),
+                ("sort_brick_calls", C.c_int64)]
 
 
 class AdjointBuffers(C.Structure):
@@ -115,6 +117,8 @@ def lib():
             "pic_last_error": [vp],
             "pic_timing_enable": [vp, i32],
             "pic_timing_read": [vp, C.POINTER(Timing)],
+            "pic_device_errors": [vp, C.POINTER(C.c_int32), i32],
+            "pic_particles_modified": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -269,6 +273,16 @@ class Context:
         array (no allocation; at most 2^22 particles per species)."""
         self._check(lib().pic_sort_static(self.h), "sort_static")
 
+    def particles_modified(self):
+        """The particle arrays were written through the bound buffers."""
+        self._check(lib().pic_particles_modified(self.h), "particles_modified")
+
+    def device_errors(self, clear=True):
+        """The sticky device error word (PIC_DEVERR_* bits); waits for the stream."""
+        v = C.c_int32(0)
+        self._check(lib().pic_device_errors(self.h, C.byref(v), int(bool(clear))), "device_errors")
+        return int(v.value)
+
     def push_deposit(self, dt, n_steps):
         self._check(lib().pic_push_deposit(self.h, float(dt), int(n_steps)), "push_deposit")
 
@@ -414,7 +428,10 @@ class Context:
         return self._view("fields", 0, 6 * s.field_points, self.dtype).view((6,) + self.padded_shape())
 
     def particle_arrays(self):
-        """Device views of the active particle set (whole capacity)."""
+        """Device views of the active particle set (whole capacity).  They are
+        writable, so the library is told that the arrays may change behind its
+        back (the next sort assumes nothing about the moves since the last)."""
+        self._check(lib().pic_particles_modified(self.h), "particles_modified")
         L = self.layout()
         buf = "p1" if L.active_set else "p0"
         cap = L.capacity

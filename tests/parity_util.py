@@ -100,3 +100,45 @@ def cached_workload(name):
         _WL_CACHE.clear()
         _WL_CACHE[name] = W.by_name(name)
     return copy.deepcopy(_WL_CACHE[name])
+
+
+def adjoint_by_chunks(g, dt, K, EB, species, lamJ, nthreads=None):
+    """The reference adjoint of the particle map over disjoint groups of
+    particles on a thread pool (the library call releases the interpreter
+    lock).  The loss is linear in the final current and the particles do not
+    act on each other within the map, so the field gradient is the sum of
+    the groups' and each particle's gradient is its group's."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    nthreads = nthreads or min(16, os.cpu_count() or 1)
+    jobs = []
+    for s, sp in enumerate(species):
+        n = sp["cell"].shape[0]
+        for idx in np.array_split(np.arange(n), nthreads):
+            if idx.size:
+                jobs.append((s, idx))
+
+    def one(job):
+        s, idx = job
+        return O.adjoint(g, dt, K, EB, [subset_species(species[s], idx)], lamJ)
+
+    with ThreadPoolExecutor(nthreads) as ex:
+        res = list(ex.map(one, jobs))
+    dEB = sum(r["dEB"] for r in res)
+    du0 = [np.zeros((sp["cell"].shape[0], 3)) for sp in species]
+    for (s, idx), r in zip(jobs, res):
+        du0[s][idx] = r["du0"][0]
+    return dict(dEB=dEB, du0=du0)
+
+
+def subset_species(sp, idx):
+    """The particles idx of one species (per-particle arrays indexed, the
+    species' constants kept)."""
+    out = {}
+    for k, v in sp.items():
+        if isinstance(v, np.ndarray) and v.ndim >= 1 and v.shape[0] == sp["cell"].shape[0]:
+            out[k] = v[idx]
+        else:
+            out[k] = v
+    return out

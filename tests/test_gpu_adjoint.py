@@ -389,3 +389,59 @@ def test_adjoint_axisymmetric_central_differences(geom):
         ip = np.sum(dEB * vE) + sum(np.sum(a * b) for a, b in zip(du, vu))
         print(f"  trial {trial}: grad.v {ip:.10e} fd {fd:.10e}", flush=True)
         assert ip == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+_K64_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_K64_24cube(prec):
+    """The adjoint workload's recipe (pair plasma in plane waves, loss weights
+    on every active edge, sorts every 4 steps inside the map) at 24^3 and
+    8 particles per cell per species, over the full K = 64 with checkpoints
+    every 8: the whole field gradient and every particle's momentum gradient
+    against the reference (which runs on a thread pool, particles split into
+    groups).  FP64: 1e-10.  FP32: over 64 steps the FP32 trajectories
+    separate from the FP64 ones (the forward current after 64 steps is
+    compared too, for scale), and a particle that crosses a cell face at
+    another step than its FP64 twin gathers other adjoint currents from then
+    on; so the bars are 5e-3 on the relative L2 of both gradients, a median
+    per-particle error below 1e-4 and 99 % of the particles within 1e-2."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[adjoint] 24^3 K=64 {prec}", flush=True)
+    wl = W.cart3d_adjoint(n=24, ppc=8, K=64, ckpt=8)
+    if prec == "f32":
+        W.round_to_f32(wl)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    if prec not in _K64_REF:
+        _K64_REF.clear()
+        _K64_REF[prec] = U.adjoint_by_chunks(g, dt, wl.K, EB, wl.species, wl.W)
+    ref = _K64_REF[prec]
+    ctx = P.from_workload(wl, prec=prec)
+    assert ctx.desc.sort_every == wl.sort_every > 0
+    ctx.forward_checkpointed(dt, wl.K, wl.ckpt_every)
+    J = ctx.current_host().astype(np.float64)
+    dEB, du0 = ctx.backward(dt, wl.K, wl.ckpt_every,
+                            torch.from_numpy(wl.W).to(device="cuda", dtype=ctx.dtype))
+    torch.cuda.synchronize()
+    dEB = dEB.double().cpu().numpy()
+    du0 = du0.double().cpu().numpy()
+    L = ctx.layout()
+    du = np.concatenate([du0[:, L.species_offset[s]:L.species_offset[s] + n].T
+                         for s, n in enumerate(r.shape[0] for r in ref["du0"])])
+    rdu = np.concatenate(ref["du0"])
+    eE = U.rel_l2(dEB, ref["dEB"])
+    eu = U.rel_l2(du, rdu)
+    pp = np.linalg.norm(du - rdu, axis=1) / np.maximum(np.linalg.norm(rdu, axis=1), 1e-30)
+    _, Jref = O.run(g, dt, wl.K, EB, wl.species, sort_every=wl.sort_every)
+    eJ = U.rel_l2(J, Jref)
+    print(f"  forward J {eJ:.2e}; dEB {eE:.2e} du0 {eu:.2e}; per particle du0: median "
+          f"{np.median(pp):.2e}, 99th percentile {np.quantile(pp, 0.99):.2e}", flush=True)
+    if prec == "f64":
+        assert eE < 1e-10 and eu < 1e-10 and eJ < 1e-10, (eE, eu, eJ)
+    else:
+        assert eE < 5e-3 and eu < 5e-3, (eE, eu)
+        assert np.median(pp) < 1e-4 and np.mean(pp < 1e-2) >= 0.99

@@ -303,3 +303,42 @@ def test_adjoint_cart3d_64_full(prec):
         # adjoint currents; such particles must stay rare
         assert np.median(e) < 1e-4
         assert np.mean(e < 1e-2) >= 0.99
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_cart3d_64_subbox_fields(prec):
+    """The full 64^3 adjoint workload over K = 8 (checkpoints every 4, sorts
+    inside the map): the field gradient on a 12^3 block of nodes against the
+    reference adjoint of the particles that start within 6 cells of the
+    block.  In 8 steps a particle moves at most 8 c dt < 2.1 cells and its
+    interpolation and deposit stencils reach 2 cells, so no other particle
+    touches the block.  Bars: 1e-10 (FP64), 1e-3 (FP32)."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    print(f"[fullsize] adjoint cart3d_64 K=8 sub-box {prec}", flush=True)
+    K, m = 8, 4
+    wl = _workload("cart3d_64_adj")
+    if prec == "f32":
+        W.round_to_f32(wl)
+    ctx = P.from_workload(wl, prec=prec)
+    g, EB = U.oracle_fields(wl, prec)
+    dt = O.dt_from_cfl(g, wl.cfl)
+    assert K * dt < 2.1
+    ctx.forward_checkpointed(dt, K, m)
+    dEB, _ = ctx.backward(dt, K, m, torch.from_numpy(wl.W).to(device="cuda", dtype=ctx.dtype))
+    torch.cuda.synchronize()
+    dEB = dEB.double().cpu().numpy()
+    lo, size, margin = 26, 12, 6
+    near = []
+    for sp in wl.species:
+        c = sp["cell"]
+        near.append(U.subset_species(sp, np.nonzero(np.all((c >= lo - margin) & (c < lo + size + margin),
+                                                           axis=1))[0]))
+    ref = U.adjoint_by_chunks(g, dt, K, EB, near, wl.W)
+    blk = (slice(None),) + (slice(W.NG + lo, W.NG + lo + size),) * 3
+    e = U.rel_l2(dEB[blk], ref["dEB"][blk])
+    print(f"  {sum(s['cell'].shape[0] for s in near)} particles near the block; dEB rel {e:.2e}",
+          flush=True)
+    tol = 1e-10 if prec == "f64" else 1e-3
+    assert e < tol
