@@ -1,5 +1,6 @@
 """Benchmark of the particle step (interpolate, rotate, Boris push, zig-zag
-deposit, per-cell sort every 20 steps) on one MI355X.
+deposit, and the per-cell sort every 5 steps of the 3D box, every 20 of the
+axisymmetric workloads) on one MI355X.
 
 Default workload: 3D Cartesian 128^3 periodic box, two species with 16
 particles per cell each (67,108,864 particles), Maxwell-Juttner theta=1 with a
@@ -36,10 +37,11 @@ def algorithmic_bytes_per_particle(dim, prec, ncells, nparticles, has_phi=False)
     return rd + wr + grid
 
 
-def measured_traffic(kernel_key):
+def measured_traffic(kernel_key, sort_every):
     """HBM bytes per launch of the push kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None once the kernel's sources differ
-    from the ones the counters were taken on."""
+    FETCH_SIZE / WRITE_SIZE summary, or None once the kernel's sources or the
+    workload generator differ from the ones the counters were taken on, or
+    the sort cadence differs."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel_key}_hbm_counters.txt")
     if not os.path.exists(path):
@@ -50,6 +52,8 @@ def measured_traffic(kernel_key):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
+        if int(kv["sort_every"]) != int(sort_every):
+            return None
         h = hashlib.sha256()
         for f in kv["kernel_sources"].split():
             with open(os.path.join(ROOT, f), "rb") as fh:
@@ -312,13 +316,14 @@ def emit(args, meta, f):
     r32, r64 = f["r32"], f["r64"]
     n = meta["particles"]
     roof = kernel_roofline_meta(meta, "f32", r32)
-    traffic = measured_traffic(f"k_push_{meta['name']}") if meta["name"] == "cart3d_128" else None
+    traffic = (measured_traffic(f"k_push_{meta['name']}", meta["sort_every"])
+               if meta["name"] == "cart3d_128" else None)
     roof.update({"traffic": traffic,
                  "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                  "traffic_GBs": (round(traffic / (r32["push_ms_avg"] * 1e-3) / 1e9, 1)
                                  if traffic else None),
-                 "kernel": "k_push<%d,%d,float>" % ({"cart": 0, "sph": 1, "qsph": 2}[meta["geom"]],
-                                                    meta["dim"])})
+                 "kernel": "k_push<%d,%d,float,false,false>" % (
+                     {"cart": 0, "sph": 1, "qsph": 2}[meta["geom"]], meta["dim"])})
     out = {
         "metric": "ns/particle/step push+deposit (fwd, adjoint) FP32 vs FP64; HBM GB/s vs peak",
         "value": round(r32["ns_per_particle_step"], 5),

@@ -12,7 +12,7 @@ constexpr int NG = 2;                  // ghost cells per side (Sec. 3.1)
 constexpr int MAXSP = 8;               // species per context
 constexpr int32_t DEAD_BIT = 0x40000000;
 constexpr int BLOCK = 256;             // threads per block of the particle kernels
-constexpr int PUSH_CHUNK = 1024;       // particles per block of the fused step kernel
+constexpr int PUSH_PPT = 4;            // fused step kernel: most particles per thread
 
 // Grid constants passed by value to kernels.
 struct GridConst {
@@ -63,6 +63,7 @@ struct SpeciesTable {
   int64_t off[MAXSP];      // element offset of the species range
   int64_t n[MAXSP];        // loaded particles
   int64_t blk0[MAXSP + 1]; // prefix of block counts over species
+  int ppt[MAXSP];          // fused step kernel: particles per thread (1, 2 or 4)
   double k[MAXSP];         // q dt / (2 m rho0)
   double qdt[MAXSP];       // q / dt
   int pusher[MAXSP];       // 0 Boris, 1 Vay, +2 guiding-centre hybrid

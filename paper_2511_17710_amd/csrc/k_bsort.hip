@@ -204,57 +204,74 @@ __global__ __launch_bounds__(BS_THREADS) void k_bs_totals(BrickSortArgs a) {
   a.tot[b] = t;
 }
 
-// exclusive scan of L values src[i] into dst (1024 threads; each takes a
-// contiguous run, read before it is written: src may be dst); returns the
-// total
-__device__ int block_scan(const int32_t *src, int32_t *dst, int L, int *sh) {
-  const int T = 1024;
-  const int C = (L + T - 1) / T;
-  const int a0 = min((int)threadIdx.x * C, L), a1 = min(a0 + C, L);
-  int s = 0;
-  for (int i = a0; i < a1; i += 8) {
-    int v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = (i + k < a1) ? src[i + k] : 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s += v[k];
-  }
+// exclusive scans of two arrays at once (src may be dst), 1024 threads, in
+// chunks of 4096 elements with 4 consecutive elements per thread; the totals
+// come back in tot[2]
+__device__ void block_scan2(const int32_t *src0, int32_t *dst0, int L0, const int32_t *src1,
+                            int32_t *dst1, int L1, int (*sh)[16], int tot[2]) {
+  constexpr int T = 1024, E = 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = s;
+  int carry0 = 0, carry1 = 0;
+  for (int base = 0; base < max(L0, L1); base += T * E) {
+    const int i0 = base + (int)threadIdx.x * E;
+    int v0[E], v1[E], s0 = 0, s1 = 0;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[w] = x;
-  __syncthreads();
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int ww = 0; ww < T / 64; ++ww) {
-    const int v = sh[ww];
-    if (ww < w) pre += v;
-    tot += v;
-  }
-  __syncthreads();
-  int run = pre + x - s;
-  for (int i = a0; i < a1; i += 8) {
-    int v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = (i + k < a1) ? src[i + k] : 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (i + k < a1) dst[i + k] = run;
-      run += v[k];
+    for (int k = 0; k < E; ++k) {
+      v0[k] = (i0 + k < L0) ? src0[i0 + k] : 0;
+      v1[k] = (i0 + k < L1) ? src1[i0 + k] : 0;
     }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      s0 += v0[k];
+      s1 += v1[k];
+    }
+    int x0 = s0, x1 = s1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y0 = __shfl_up(x0, o, 64), y1 = __shfl_up(x1, o, 64);
+      if (lane >= o) {
+        x0 += y0;
+        x1 += y1;
+      }
+    }
+    if (lane == 63) {
+      sh[0][w] = x0;
+      sh[1][w] = x1;
+    }
+    __syncthreads();
+    int p0 = 0, p1 = 0, t0 = 0, t1 = 0;
+#pragma unroll
+    for (int ww = 0; ww < T / 64; ++ww) {
+      const int a = sh[0][ww], b = sh[1][ww];
+      if (ww < w) {
+        p0 += a;
+        p1 += b;
+      }
+      t0 += a;
+      t1 += b;
+    }
+    __syncthreads();
+    int r0 = carry0 + p0 + x0 - s0, r1 = carry1 + p1 + x1 - s1;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      if (i0 + k < L0) dst0[i0 + k] = r0;
+      if (i0 + k < L1) dst1[i0 + k] = r1;
+      r0 += v0[k];
+      r1 += v1[k];
+    }
+    carry0 += t0;
+    carry1 += t1;
   }
-  return tot;
+  tot[0] = carry0;
+  tot[1] = carry1;
 }
 
 __global__ __launch_bounds__(1024) void k_bs_scan(BrickSortArgs a) {
-  __shared__ int sh[16];
+  __shared__ int sh[2][16];
   if (a.flag[0]) return;
-  const int live = block_scan(a.tot, a.bnew, a.nb, sh);
-  const int dead = block_scan(a.dpre, a.dpre, a.nb + 1, sh);
+  int tot[2];
+  block_scan2(a.tot, a.bnew, a.nb, a.dpre, a.dpre, a.nb + 1, sh, tot);
+  const int live = tot[0], dead = tot[1];
   if (threadIdx.x == 0) {
     a.bnew[a.nb] = live;
     a.bnew[a.nb + 1] = live + dead;

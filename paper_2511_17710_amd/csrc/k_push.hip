@@ -1,9 +1,9 @@
 // k_push.hip -- fused particle step: interpolate, rotate, Boris, move, deposit
 // (arXiv 2511.17710, Sec. 2.3 steps 3-8), one launch for all species.
 //
-// A block owns CHUNK consecutive particles of one species (4 per thread,
-// loaded with 16-byte vector accesses, or through the permutation of a sort
-// on the step that follows it).  Particles are kept in brick order by the
+// A block owns a chunk of consecutive particles of one species (4 per
+// thread, loaded with 16-byte vector accesses, or fewer for sparse species;
+// through the permutation of a sort on the step that follows it).  Particles are kept in brick order by the
 // per-cell sort, so the chunk's cells form a compact box.  One LDS buffer
 // serves in turn as the block's copy of the fields over that box (when it
 // fits) for the push pass, and as the block's current tile over the box
@@ -19,9 +19,7 @@
 
 namespace picstep {
 
-constexpr int PPT = 4;                  // particles per thread
-constexpr int CHUNK = PUSH_CHUNK;       // particles per block
-static_assert(BLOCK * PPT == CHUNK, "chunk layout");
+constexpr int PPT = PUSH_PPT;  // most particles per thread (the species' ppt)
 // LDS buffer per block (field copy, then current tile), sized so that the
 // blocks a CU holds at once share its 160 KB: the FP32 instances run 4 blocks
 // per CU, the FP64 ones 2 (their registers allow no more).
@@ -89,6 +87,7 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 // one plane of bricks at a time, so the particles that came from the plane
 // before are read while it is still cached; under the XCD order they were
 // last touched many L2 capacities earlier (push 3.4 -> 3.2 ms on that step).
+template <bool SPARSE>
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0,
                                              bool plain) {
   // blk0[MAXSP] = all blocks
@@ -97,7 +96,7 @@ __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
     if (t < sp.nspec && b >= sp.blk0[t]) s = t;
-  c0 = (b - sp.blk0[s]) * CHUNK;
+  c0 = (b - sp.blk0[s]) * ((int64_t)BLOCK * (SPARSE ? sp.ppt[s] : PPT));
   return c0 < sp.n[s];
 }
 
@@ -318,8 +317,10 @@ constexpr int push_waves() {
 }
 
 // PUSHERS: some species uses another pusher than Boris (a separate instance,
-// so the plain Boris kernel carries no code for them).
-template <int GEOM, int DIM, class Real, bool PUSHERS>
+// so the plain Boris kernel carries no code for them).  SPARSE: some species
+// has fewer than 4 particles per thread (the dense instance keeps the
+// constant layout of 4).
+template <int GEOM, int DIM, class Real, bool PUSHERS, bool SPARSE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(push_waves<GEOM, DIM, Real>(), 8)))
 void k_push(StepArgs<Real> A) {
   using Acc = typename TileAcc<Real>::type;
@@ -337,9 +338,10 @@ void k_push(StepArgs<Real> A) {
   const GridConst &g = A.g;
   int s;
   int64_t c0;
-  if (!locate_chunk(A.sp, s, c0, A.perm != nullptr)) return;  // uniform over the block
-  const int64_t first = c0 + (int64_t)threadIdx.x * PPT;
-  const int cnt = (int)max((int64_t)0, min((int64_t)PPT, A.sp.n[s] - first));
+  if (!locate_chunk<SPARSE>(A.sp, s, c0, A.perm != nullptr)) return;  // uniform over the block
+  const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
+  const int64_t first = c0 + (int64_t)threadIdx.x * ppt;
+  const int cnt = (int)max((int64_t)0, min((int64_t)ppt, A.sp.n[s] - first));
   const int64_t p0 = A.sp.off[s] + first;
 
   int32_t cl[PPT];
@@ -620,8 +622,8 @@ void k_push(StepArgs<Real> A) {
   // |dx3|) to any tile value (its segment fluxes along a dimension sum to
   // its displacement there, span the largest; shape weights are at most 1;
   // the out-of-plane current of 2D grids carries dx3).  With B 2^esc < 2^49
-  // one contribution stays below the 2^51 of the rounding and the CHUNK
-  // particles of the block below 2^60, and small displacements (cold plasma)
+  // one contribution stays below the 2^51 of the rounding and the (at most
+  // 1024) particles of the block below 2^60, and small displacements (cold plasma)
   // keep the full 48-bit resolution relative to the largest of the block.
   int esc = 0;
   if (sizeof(Acc) == 8 && sizeof(Real) == 4) {
@@ -701,17 +703,17 @@ void k_push(StepArgs<Real> A) {
   }
 }
 
-template <class Real, bool PUSHERS>
+template <class Real, bool PUSHERS, bool SPARSE>
 hipError_t launch_push_instance(const StepArgs<Real> &a, dim3 grid, dim3 block, hipStream_t s) {
   if (a.g.geom == 0) {
     if (a.g.dim == 2)
-      hipLaunchKernelGGL((k_push<0, 2, Real, PUSHERS>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_push<0, 2, Real, PUSHERS, SPARSE>), grid, block, 0, s, a);
     else
-      hipLaunchKernelGGL((k_push<0, 3, Real, PUSHERS>), grid, block, 0, s, a);
+      hipLaunchKernelGGL((k_push<0, 3, Real, PUSHERS, SPARSE>), grid, block, 0, s, a);
   } else if (a.g.geom == 1) {
-    hipLaunchKernelGGL((k_push<1, 2, Real, PUSHERS>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_push<1, 2, Real, PUSHERS, SPARSE>), grid, block, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_push<2, 2, Real, PUSHERS>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_push<2, 2, Real, PUSHERS, SPARSE>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
@@ -721,10 +723,15 @@ hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s) {
   const int64_t nblk = a.sp.blk0[a.sp.nspec];
   if (nblk == 0) return hipSuccess;
   dim3 grid((unsigned)nblk), block(BLOCK);
-  bool pushers = false;
-  for (int t = 0; t < a.sp.nspec; ++t) pushers = pushers || a.sp.pusher[t] != 0;
-  return pushers ? launch_push_instance<Real, true>(a, grid, block, s)
-                 : launch_push_instance<Real, false>(a, grid, block, s);
+  bool pushers = false, sparse = false;
+  for (int t = 0; t < a.sp.nspec; ++t) {
+    pushers = pushers || a.sp.pusher[t] != 0;
+    sparse = sparse || a.sp.ppt[t] != PPT;
+  }
+  // the other pushers take the general layout too (three instances, not four)
+  if (pushers) return launch_push_instance<Real, true, true>(a, grid, block, s);
+  return sparse ? launch_push_instance<Real, false, true>(a, grid, block, s)
+                : launch_push_instance<Real, false, false>(a, grid, block, s);
 }
 
 template hipError_t launch_push_deposit<float>(const StepArgs<float> &, hipStream_t);

@@ -171,6 +171,24 @@ SpeciesTable species_table(const pic_ctx *c, double dt, int64_t per_block) {
   return t;
 }
 
+// The fused step kernel's chunks: BLOCK threads of 1, 2 or 4 particles.  A
+// chunk of the sorted order covers about chunk / ppc cells, which the LDS
+// tiles must hold after the drift between sorts: 4 per thread (1024, half a
+// brick at 16 per cell) down to 1 (256) for species below 3 particles per
+// cell on average, where a 1024-chunk would stretch over several bricks.
+SpeciesTable push_species_table(const pic_ctx *c, double dt) {
+  SpeciesTable t = species_table(c, dt, BLOCK * PUSH_PPT);
+  const double ncells = (double)c->g.n[0] * c->g.n[1] * c->g.n[2];
+  for (int s = 0; s < c->nspec; ++s) {
+    const double ppc = (double)t.n[s] / ncells;
+    t.ppt[s] = ppc >= 8.0 ? 4 : (ppc >= 3.0 ? 2 : 1);
+    const int64_t chunk = (int64_t)BLOCK * t.ppt[s];
+    t.blk0[s + 1] = t.blk0[s] + (t.n[s] + chunk - 1) / chunk;
+  }
+  for (int s = c->nspec; s < MAXSP; ++s) t.blk0[s + 1] = t.blk0[c->nspec];
+  return t;
+}
+
 // records the start event of a timed region; returns its index or -1
 int ev_begin(pic_ctx *c, int kind) {
   if (!c->timing) return -1;
@@ -322,7 +340,7 @@ template <class Real>
 pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   StepArgs<Real> a{};
   a.g = c->g;
-  a.sp = species_table(c, dt, PUSH_CHUNK);
+  a.sp = push_species_table(c, dt);
   a.p = pset_of<Real>(c, c->active);
   a.perm = nullptr;
   if (c->perm_pending) {  // read through the pending sort, write the other set
