@@ -436,6 +436,13 @@ pic_status pic_device_errors(pic_ctx *ctx, int32_t *flags, int32_t clear);
  * the particle arrays; the fast form assumes moves of at most one brick). */
 pic_status pic_particles_modified(pic_ctx *ctx);
 
+/* Debug launch mode of the fused step kernel (race detection): with on != 0
+ * every push launches its blocks one at a time, each alone on the GPU, in
+ * the plain block order.  Particle results are identical to the normal
+ * launch (the current differs only by the order of its floating-point
+ * additions across blocks).  Slow: for small test grids. */
+pic_status pic_debug_serial(pic_ctx *ctx, int32_t on);
+
 /* Message of the last failing call on this context (never NULL). */
 const char *pic_last_error(const pic_ctx *ctx);
 

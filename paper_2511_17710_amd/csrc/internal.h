@@ -90,6 +90,10 @@ struct StepArgs {
   // the sorted, advanced particles into p
   const int32_t *perm;
   PSet<Real> src;
+  // debug launch with one block in flight: this launch is block block_base
+  // of the whole grid (serial != 0; then blocks take the plain order)
+  int64_t block_base;
+  int serial;
 };
 
 // reverse step: recompute the forward step from the stored state and
@@ -110,7 +114,7 @@ struct AdjArgs {
 
 // ---- launchers (defined in the .hip files) ----
 template <class Real>
-hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s);
+hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s, bool serial = false);
 template <class Real>
 hipError_t launch_adjoint_step(const AdjArgs<Real> &a, hipStream_t s);
 template <class Real>

@@ -89,9 +89,10 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 // last touched many L2 capacities earlier (push 3.4 -> 3.2 ms on that step).
 template <bool SPARSE>
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0,
-                                             bool plain) {
+                                             bool plain, int64_t base) {
   // blk0[MAXSP] = all blocks
-  const int64_t b = plain ? (int64_t)blockIdx.x : xcd_chunk(blockIdx.x, sp.blk0[MAXSP]);
+  const int64_t bid = base + (int64_t)blockIdx.x;
+  const int64_t b = plain ? bid : xcd_chunk(bid, sp.blk0[MAXSP]);
   s = 0;
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
@@ -338,7 +339,8 @@ void k_push(StepArgs<Real> A) {
   const GridConst &g = A.g;
   int s;
   int64_t c0;
-  if (!locate_chunk<SPARSE>(A.sp, s, c0, A.perm != nullptr)) return;  // uniform over the block
+  if (!locate_chunk<SPARSE>(A.sp, s, c0, A.perm != nullptr || A.serial, A.block_base))
+    return;  // uniform over the block
   const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
   const int64_t first = c0 + (int64_t)threadIdx.x * ppt;
   const int cnt = (int)max((int64_t)0, min((int64_t)ppt, A.sp.n[s] - first));
@@ -718,23 +720,37 @@ hipError_t launch_push_instance(const StepArgs<Real> &a, dim3 grid, dim3 block, 
   return hipGetLastError();
 }
 
+// serial: the debug launch with one block in flight (one launch per block,
+// in the plain block order), for comparisons that rule out interference
+// between blocks
 template <class Real>
-hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s) {
+hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s, bool serial) {
   const int64_t nblk = a.sp.blk0[a.sp.nspec];
   if (nblk == 0) return hipSuccess;
-  dim3 grid((unsigned)nblk), block(BLOCK);
   bool pushers = false, sparse = false;
   for (int t = 0; t < a.sp.nspec; ++t) {
     pushers = pushers || a.sp.pusher[t] != 0;
     sparse = sparse || a.sp.ppt[t] != PPT;
   }
-  // the other pushers take the general layout too (three instances, not four)
-  if (pushers) return launch_push_instance<Real, true, true>(a, grid, block, s);
-  return sparse ? launch_push_instance<Real, false, true>(a, grid, block, s)
-                : launch_push_instance<Real, false, false>(a, grid, block, s);
+  auto launch = [&](const StepArgs<Real> &x, dim3 grid) {
+    const dim3 block(BLOCK);
+    // the other pushers take the general layout too (three instances, not four)
+    if (pushers) return launch_push_instance<Real, true, true>(x, grid, block, s);
+    return sparse ? launch_push_instance<Real, false, true>(x, grid, block, s)
+                  : launch_push_instance<Real, false, false>(x, grid, block, s);
+  };
+  if (!serial) return launch(a, dim3((unsigned)nblk));
+  StepArgs<Real> x = a;
+  x.serial = 1;
+  for (int64_t b = 0; b < nblk; ++b) {
+    x.block_base = b;
+    const hipError_t e = launch(x, dim3(1));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-template hipError_t launch_push_deposit<float>(const StepArgs<float> &, hipStream_t);
-template hipError_t launch_push_deposit<double>(const StepArgs<double> &, hipStream_t);
+template hipError_t launch_push_deposit<float>(const StepArgs<float> &, hipStream_t, bool);
+template hipError_t launch_push_deposit<double>(const StepArgs<double> &, hipStream_t, bool);
 
 }  // namespace picstep

@@ -74,6 +74,7 @@ struct pic_ctx {
   double moved = 0.0;
   double max_inv_dx = 0.0;  // Cartesian: largest 1 / dx
   bool timing = false;
+  bool debug_serial = false;  // the fused step kernel launched one block at a time
   struct Ev {
     hipEvent_t a, b;
     int kind;  // 0 push, 1 sort, 2 adjoint
@@ -363,7 +364,7 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   if (dep) e = launch_zero<Real>(a.J, 3 * c->g.npts, c->stream);
   if (e != hipSuccess) return hipchk(c, e, "zero J");
   const int ev = dep ? ev_begin(c, 0) : -1;
-  e = launch_push_deposit<Real>(a, c->stream);
+  e = launch_push_deposit<Real>(a, c->stream, c->debug_serial);
   ev_end(c, ev);
   if (e != hipSuccess) return hipchk(c, e, "push_deposit");
   if (a.perm) {
@@ -1521,6 +1522,12 @@ pic_status pic_device_errors(pic_ctx *c, int32_t *flags, int32_t clear) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess && clear) e = launch_zero<int32_t>(dev, 1, c->stream);
   return hipchk(c, e, "device_errors");
+}
+
+pic_status pic_debug_serial(pic_ctx *c, int32_t on) {
+  if (!c) return PIC_E_ARG;
+  c->debug_serial = on != 0;
+  return PIC_OK;
 }
 
 pic_status pic_particles_modified(pic_ctx *c) {

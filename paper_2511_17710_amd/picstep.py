@@ -119,6 +119,7 @@ def lib():
             "pic_timing_read": [vp, C.POINTER(Timing)],
             "pic_device_errors": [vp, C.POINTER(C.c_int32), i32],
             "pic_particles_modified": [vp],
+            "pic_debug_serial": [vp, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -272,6 +273,10 @@ class Context:
         """pic_sort with the radix temporaries in the library's static device
         array (no allocation; at most 2^22 particles per species)."""
         self._check(lib().pic_sort_static(self.h), "sort_static")
+
+    def debug_serial(self, on=True):
+        """Debug launch mode: the fused step kernel one block at a time."""
+        self._check(lib().pic_debug_serial(self.h, int(bool(on))), "debug_serial")
 
     def particles_modified(self):
         """The particle arrays were written through the bound buffers."""
