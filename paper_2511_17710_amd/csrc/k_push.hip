@@ -19,13 +19,19 @@
 
 namespace picstep {
 
-constexpr int PPT = PUSH_PPT;  // most particles per thread (the species' ppt)
+// most particles per thread of the dense instance: 4 in FP32 contexts, 2 in
+// FP64 ones (their registers: 4 particles need about 240 per lane, which
+// holds a SIMD at 2 waves)
+template <class Real>
+constexpr int push_ppt() {
+  return sizeof(Real) == 4 ? 4 : 2;
+}
 // LDS buffer per block (field copy, then current tile), sized so that the
-// blocks a CU holds at once share its 160 KB: the FP32 instances run 4 blocks
-// per CU, the FP64 ones 2 (their registers allow no more).
+// blocks a CU holds at once share its 160 KB: 4 blocks per CU (the FP64
+// chunks of 512 particles need half the FP32 field copy's points).
 template <class Real>
 constexpr int tile_bytes() {
-  return sizeof(Real) == 8 ? 79872 : 39936;
+  return 39936;
 }
 
 // ---------------------------------------------------------------- vector I/O
@@ -59,23 +65,59 @@ __device__ __forceinline__ void st4(double *p, const double v[4]) {
   *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
   *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
 }
+__device__ __forceinline__ void ld2(const double *p, double v[2]) {
+  const double2 a = *reinterpret_cast<const double2 *>(p);
+  v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void ld2(const int32_t *p, int32_t v[2]) {
+  const int2 a = *reinterpret_cast<const int2 *>(p);
+  v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void ld2(const float *p, float v[2]) {
+  const float2 a = *reinterpret_cast<const float2 *>(p);
+  v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void ld2(const uint32_t *p, uint32_t v[2]) {
+  const uint2 a = *reinterpret_cast<const uint2 *>(p);
+  v[0] = a.x; v[1] = a.y;
+}
+__device__ __forceinline__ void st2(double *p, const double v[2]) {
+  *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+}
+__device__ __forceinline__ void st2(int32_t *p, const int32_t v[2]) {
+  *reinterpret_cast<int2 *>(p) = make_int2(v[0], v[1]);
+}
+__device__ __forceinline__ void st2(float *p, const float v[2]) {
+  *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+}
+__device__ __forceinline__ void st2(uint32_t *p, const uint32_t v[2]) {
+  *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[1]);
+}
+template <int N, class T>
+__device__ __forceinline__ void ldv(const T *p, T v[N]) {
+  if constexpr (N == 4) ld4(p, v); else ld2(p, v);
+}
+template <int N, class T>
+__device__ __forceinline__ void stv(T *p, const T v[N]) {
+  if constexpr (N == 4) st4(p, v); else st2(p, v);
+}
 
-template <class T>
-__device__ __forceinline__ void load_n(const T *p, int cnt, T v[4], T fill) {
-  if (cnt == PPT) {
-    ld4(p, v);
+template <int N, class T>
+__device__ __forceinline__ void load_n(const T *p, int cnt, T v[N], T fill) {
+  if (cnt == N) {
+    ldv<N>(p, v);
   } else {
 #pragma unroll
-    for (int r = 0; r < PPT; ++r) v[r] = (r < cnt) ? p[r] : fill;
+    for (int r = 0; r < N; ++r) v[r] = (r < cnt) ? p[r] : fill;
   }
 }
-template <class T>
-__device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
-  if (cnt == PPT) {
-    st4(p, v);
+template <int N, class T>
+__device__ __forceinline__ void store_n(T *p, int cnt, const T v[N]) {
+  if (cnt == N) {
+    stv<N>(p, v);
   } else {
 #pragma unroll
-    for (int r = 0; r < PPT; ++r)
+    for (int r = 0; r < N; ++r)
       if (r < cnt) p[r] = v[r];
   }
 }
@@ -87,7 +129,7 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[4]) {
 // one plane of bricks at a time, so the particles that came from the plane
 // before are read while it is still cached; under the XCD order they were
 // last touched many L2 capacities earlier (push 3.4 -> 3.2 ms on that step).
-template <bool SPARSE>
+template <bool SPARSE, int PPT>
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0,
                                              bool plain, int64_t base) {
   // blk0[MAXSP] = all blocks
@@ -308,13 +350,14 @@ __device__ __forceinline__ void deposit_particle(const StepArgs<Real> &A, int s,
 }
 
 // ---------------------------------------------------------------- the kernel
-// Waves per SIMD the register allocation must allow: the FP32 LDS buffer
+// Waves per SIMD the register allocation must allow: the LDS buffer
 // already limits a CU to 4 blocks of 4 waves, and the Cartesian FP32 kernel
 // runs faster capped at that occupancy (128 VGPRs) than uncapped at 3 waves;
-// the other instances would spill heavily.
+// the FP64 instances (2 particles per thread) are held to 3 (168 VGPRs); the
+// other instances would spill heavily.
 template <int GEOM, int DIM, class Real>
 constexpr int push_waves() {
-  return (GEOM == 0 && sizeof(Real) == 4) ? 4 : 1;
+  return sizeof(Real) == 8 ? 3 : (GEOM == 0 ? 4 : 1);
 }
 
 // PUSHERS: some species uses another pusher than Boris (a separate instance,
@@ -339,7 +382,8 @@ void k_push(StepArgs<Real> A) {
   const GridConst &g = A.g;
   int s;
   int64_t c0;
-  if (!locate_chunk<SPARSE>(A.sp, s, c0, A.perm != nullptr || A.serial, A.block_base))
+  constexpr int PPT = push_ppt<Real>();
+  if (!locate_chunk<SPARSE, PPT>(A.sp, s, c0, A.perm != nullptr || A.serial, A.block_base))
     return;  // uniform over the block
   const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
   const int64_t first = c0 + (int64_t)threadIdx.x * ppt;
@@ -368,20 +412,20 @@ void k_push(StepArgs<Real> A) {
       ph[r] = (ok && GEOM != 0) ? A.src.phi[js[r]] : (Real)0;
       idv[r] = ok ? A.src.id[js[r]] : 0;
     }
-    store_n(A.p.id + p0, cnt, idv);
+    store_n<PPT>(A.p.id + p0, cnt, idv);
   } else {
-    load_n(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
+    load_n<PPT>(A.p.cell + p0, cnt, cl, (int32_t)DEAD_BIT);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) load_n(A.p.offs[a] + p0, cnt, qd[a], (OffT<Real>)0);
+    for (int a = 0; a < DIM; ++a) load_n<PPT>(A.p.offs[a] + p0, cnt, qd[a], (OffT<Real>)0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) load_n(A.p.u[a] + p0, cnt, uu[a], (Real)0);
-    load_n(A.p.w + p0, cnt, ww, (Real)0);
-    if (GEOM != 0) load_n(A.p.phi + p0, cnt, ph, (Real)0);
+    for (int a = 0; a < 3; ++a) load_n<PPT>(A.p.u[a] + p0, cnt, uu[a], (Real)0);
+    load_n<PPT>(A.p.w + p0, cnt, ww, (Real)0);
+    if (GEOM != 0) load_n<PPT>(A.p.phi + p0, cnt, ph, (Real)0);
   }
   if (A.write_prev) {
-    store_n(A.prev_cell + p0, cnt, cl);
+    store_n<PPT>(A.prev_cell + p0, cnt, cl);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) store_n(A.prev_offs[a] + p0, cnt, qd[a]);
+    for (int a = 0; a < DIM; ++a) store_n<PPT>(A.prev_offs[a] + p0, cnt, qd[a]);
   }
 
   // bounding box of the chunk's current cells; a periodic dimension whose
@@ -402,13 +446,13 @@ void k_push(StepArgs<Real> A) {
   block_minmax3(lo, hi, red);
   if (lo[0] > hi[0]) {  // no live particle in the chunk (uniform)
     if (A.perm) {       // still move the frozen particles into the sorted set
-      store_n(A.p.cell + p0, cnt, cl);
+      store_n<PPT>(A.p.cell + p0, cnt, cl);
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
+      for (int a = 0; a < DIM; ++a) store_n<PPT>(A.p.offs[a] + p0, cnt, qd[a]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
-      store_n(A.p.w + p0, cnt, ww);
-      if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+      for (int a = 0; a < 3; ++a) store_n<PPT>(A.p.u[a] + p0, cnt, uu[a]);
+      store_n<PPT>(A.p.w + p0, cnt, ww);
+      if (GEOM != 0) store_n<PPT>(A.p.phi + p0, cnt, ph);
     }
     return;
   }
@@ -606,13 +650,13 @@ void k_push(StepArgs<Real> A) {
     push_pass(std::true_type{});
   if (nonfinite && A.err) atomicOr(A.err, PIC_DEVERR_NONFINITE);
 
-  store_n(A.p.cell + p0, cnt, cl);
+  store_n<PPT>(A.p.cell + p0, cnt, cl);
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) store_n(A.p.offs[a] + p0, cnt, qd[a]);
+  for (int a = 0; a < DIM; ++a) store_n<PPT>(A.p.offs[a] + p0, cnt, qd[a]);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) store_n(A.p.u[a] + p0, cnt, uu[a]);
-  if (A.perm) store_n(A.p.w + p0, cnt, ww);  // the weights move with the sort
-  if (GEOM != 0) store_n(A.p.phi + p0, cnt, ph);
+  for (int a = 0; a < 3; ++a) store_n<PPT>(A.p.u[a] + p0, cnt, uu[a]);
+  if (A.perm) store_n<PPT>(A.p.w + p0, cnt, ww);  // the weights move with the sort
+  if (GEOM != 0) store_n<PPT>(A.p.phi + p0, cnt, ph);
   if (!use_tile) return;  // uniform
 
   // the field copy is done with: the LDS buffer becomes the current tile
@@ -730,7 +774,7 @@ hipError_t launch_push_deposit(const StepArgs<Real> &a, hipStream_t s, bool seri
   bool pushers = false, sparse = false;
   for (int t = 0; t < a.sp.nspec; ++t) {
     pushers = pushers || a.sp.pusher[t] != 0;
-    sparse = sparse || a.sp.ppt[t] != PPT;
+    sparse = sparse || a.sp.ppt[t] != push_ppt<Real>();
   }
   auto launch = [&](const StepArgs<Real> &x, dim3 grid) {
     const dim3 block(BLOCK);

@@ -180,9 +180,10 @@ SpeciesTable species_table(const pic_ctx *c, double dt, int64_t per_block) {
 SpeciesTable push_species_table(const pic_ctx *c, double dt) {
   SpeciesTable t = species_table(c, dt, BLOCK * PUSH_PPT);
   const double ncells = (double)c->g.n[0] * c->g.n[1] * c->g.n[2];
+  const int most = c->eb == 4 ? 4 : 2;  // the dense instance's layout (FP64: 2)
   for (int s = 0; s < c->nspec; ++s) {
     const double ppc = (double)t.n[s] / ncells;
-    t.ppt[s] = ppc >= 8.0 ? 4 : (ppc >= 3.0 ? 2 : 1);
+    t.ppt[s] = std::min(most, ppc >= 8.0 ? 4 : (ppc >= 3.0 ? 2 : 1));
     const int64_t chunk = (int64_t)BLOCK * t.ppt[s];
     t.blk0[s + 1] = t.blk0[s] + (t.n[s] + chunk - 1) / chunk;
   }
