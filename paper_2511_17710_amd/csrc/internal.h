@@ -13,6 +13,13 @@ constexpr int MAXSP = 8;               // species per context
 constexpr int32_t DEAD_BIT = 0x40000000;
 constexpr int BLOCK = 256;             // threads per block of the particle kernels
 constexpr int PUSH_PPT = 4;            // fused step kernel: most particles per thread
+// reverse-step kernel: particles per thread (FP32 1: its registers are full
+// with one; FP64 2)
+template <class Real>
+constexpr int adj_ppt() {
+  return sizeof(Real) == 4 ? 1 : 2;
+}
+constexpr int adj_chunk(size_t elem_bytes) { return BLOCK * (elem_bytes == 4 ? 1 : 2); }
 
 // Grid constants passed by value to kernels.
 struct GridConst {

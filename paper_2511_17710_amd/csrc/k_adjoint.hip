@@ -345,7 +345,9 @@ __device__ __forceinline__ void axi_particle_rev(const AdjArgs<Real> &A, int s, 
   A.lam_phi[p] = (Real)phib;
 }
 
-// One particle per thread, BLOCK particles per block in XCD-aware order.  The
+// adj_ppt particles per thread (BLOCK apart; 1 in FP32, 2 in FP64), in
+// XCD-aware order: the block's field and dL/dJ copies and its tile flush
+// serve them all.  The
 // scatter into dL/dE, dL/dB (the adjoint of the interpolation) goes to an LDS
 // tile over the block's cells, accumulated like the forward current (64-bit
 // fixed point in FP32 builds, scaled by the block's largest |dL/dF|) and
@@ -364,6 +366,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(adj_waves
 void k_adjoint(AdjArgs<Real> A) {
   using PS = Pos<Real>;
   using Acc = typename TileAcc<Real>::type;
+  constexpr int APT = adj_ppt<Real>();
   constexpr int TILE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Acc);
   constexpr int STAGE_VALS = adj_tile_bytes<Real>() / (int)sizeof(Real);
   __shared__ union {
@@ -378,43 +381,72 @@ void k_adjoint(AdjArgs<Real> A) {
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
     if (t < A.sp.nspec && blk >= A.sp.blk0[t]) s = t;
-  const int64_t local = (blk - A.sp.blk0[s]) * BLOCK + threadIdx.x;
-  const bool inrange = local < A.sp.n[s];
-  const int64_t p = A.sp.off[s] + (inrange ? local : 0);
-  const int32_t cc = inrange ? A.p.cell[p] : (int32_t)DEAD_BIT;
-  // a frozen (dead) particle maps to itself: its adjoints pass through
-  const bool live = !(cc & DEAD_BIT);
-  int i[3];
-  cell_decode(g, cc, i);
+  // the thread's particles: APT of the block's chunk, BLOCK apart
+  const int64_t c0 = (blk - A.sp.blk0[s]) * (int64_t)(BLOCK * APT);
+  int64_t pr[APT];
+  int32_t ccr[APT];
+#pragma unroll
+  for (int r = 0; r < APT; ++r) {
+    const int64_t local = c0 + (int64_t)r * BLOCK + threadIdx.x;
+    const bool inrange = local < A.sp.n[s];
+    pr[r] = A.sp.off[s] + (inrange ? local : 0);
+    // a frozen (dead) particle maps to itself: its adjoints pass through
+    ccr[r] = inrange ? A.p.cell[pr[r]] : (int32_t)DEAD_BIT;
+  }
 
   // ---------------- the block's box and its LDS tile (stencils reach i-1 .. i+1)
   int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-  if (live) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = i[d];
+  for (int r = 0; r < APT; ++r) {
+    if (ccr[r] & DEAD_BIT) continue;
+    int i[3];
+    cell_decode(g, ccr[r], i);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], i[d]);
+      hi[d] = max(hi[d], i[d]);
+    }
   }
   block_minmax3(lo, hi, red);
   if (lo[0] > hi[0]) return;  // no live particle in the block (uniform)
-  int ib[3] = {i[0], i[1], i[2]};
+  // periodic dimensions whose cells span more than half the box are
+  // unwrapped (cells below N/2 shifted by +N)
+  int shift[3] = {0, 0, 0};
   if (GEOM == 0) {
-    int shift[3] = {0, 0, 0};
     bool any = false;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       shift[d] = (hi[d] - lo[d] > (g.n[d] >> 1)) ? 1 : 0;
       any = any || shift[d];
-      if (shift[d] && ib[d] < (g.n[d] >> 1)) ib[d] += g.n[d];
     }
     if (any) {  // a block straddling a periodic boundary: box of the unwrapped cells
       __syncthreads();
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        lo[d] = live ? ib[d] : INT32_MAX;
-        hi[d] = live ? ib[d] : INT32_MIN;
+        lo[d] = INT32_MAX;
+        hi[d] = INT32_MIN;
+      }
+#pragma unroll
+      for (int r = 0; r < APT; ++r) {
+        if (ccr[r] & DEAD_BIT) continue;
+        int i[3];
+        cell_decode(g, ccr[r], i);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int v = i[d] + ((shift[d] && i[d] < (g.n[d] >> 1)) ? g.n[d] : 0);
+          lo[d] = min(lo[d], v);
+          hi[d] = max(hi[d], v);
+        }
       }
       block_minmax3(lo, hi, red);
     }
   }
+  // unwrapped minus stored cell coordinates of a particle
+  auto unwrap = [&](const int i[3], int dsh[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      dsh[d] = (GEOM == 0 && shift[d] && i[d] < (g.n[d] >> 1)) ? g.n[d] : 0;
+  };
   int t0[3] = {0, 0, 0}, ts[3] = {1, 1, 1}, j0[3] = {0, 0, 0}, js[3] = {1, 1, 1};
   int T = 1, TJ = 1;
 #pragma unroll
@@ -433,9 +465,17 @@ void k_adjoint(AdjArgs<Real> A) {
     for (int d = 0; d < DIM; ++d) t0[d] = lo[d] - 1;
   } else {  // largest cube (square) centred on the block's mean cell
     __syncthreads();
-    int sum[3] = {0, 0, 0}, nl[3] = {live ? 1 : 0, 0, 0};
+    int sum[3] = {0, 0, 0}, nl[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) sum[d] = live ? ib[d] : 0;
+    for (int r = 0; r < APT; ++r) {
+      if (ccr[r] & DEAD_BIT) continue;
+      int i[3], dsh[3];
+      cell_decode(g, ccr[r], i);
+      unwrap(i, dsh);
+      nl[0] += 1;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sum[d] += i[d] + dsh[d];
+    }
     block_sum3(sum, red);
     __syncthreads();
     block_sum3(nl, red);
@@ -454,12 +494,30 @@ void k_adjoint(AdjArgs<Real> A) {
     if (A.lamJ) stage_box<GEOM, DIM, Real>(g, A.lamJ, 3, j0, js, lds.f + 6 * T);
     __syncthreads();
   }
-  const int dsh[3] = {ib[0] - i[0], ib[1] - i[1], ib[2] - i[2]};  // unwrapped - stored
+  FieldTile<Real> ft;
+  ft.F = lds.f;
+  ft.T = T;
+  ft.sy = ts[0];
+  ft.sz = ts[0] * ts[1];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ft.o[a] = t0[a];
+    ft.ts[a] = ts[a];
+  }
 
-  Real Fbar[6] = {0, 0, 0, 0, 0, 0};
-  Stencil1<Real> st[3];
+  Real Fbr[APT][6];
   float bmax = 0.0f;
-  if (live) {
+#pragma unroll
+  for (int r = 0; r < APT; ++r) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Fbr[r][c] = (Real)0;
+    if (ccr[r] & DEAD_BIT) continue;
+    const int64_t p = pr[r];
+    int i[3], dsh[3];
+    cell_decode(g, ccr[r], i);
+    unwrap(i, dsh);
+    Real *Fbar = Fbr[r];
+    Stencil1<Real> st[3];
     OffT<Real> q[3] = {(OffT<Real>)0, (OffT<Real>)0, (OffT<Real>)0};
     Real d[3] = {0, 0, 0};
 #pragma unroll
@@ -469,16 +527,6 @@ void k_adjoint(AdjArgs<Real> A) {
       st[a] = stencil1(i[a], d[a]);
     }
     // ---------------- forward recompute of step 3 (interpolation)
-    FieldTile<Real> ft;
-    ft.F = lds.f;
-    ft.T = T;
-    ft.sy = ts[0];
-    ft.sz = ts[0] * ts[1];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      ft.o[a] = t0[a];
-      ft.ts[a] = ts[a];
-    }
     Real F[6];
     if (stage)
       interp6_tile<DIM, Real>(ft, dsh, st, F);
@@ -550,12 +598,12 @@ void k_adjoint(AdjArgs<Real> A) {
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
-  }  // live
+  }
 
   // ---------------- scatter of dL/dF into the tile (or global memory)
   // Fixed-point scale 2^esc (FP32): one particle adds at most max|dL/dF| to a
   // tile value (interpolation weights are at most 1), so with B 2^esc < 2^49
-  // the BLOCK particles of the block stay below 2^57.
+  // the (at most 2 BLOCK) particles of the block stay below 2^58.
   // the copies are done with: the buffer becomes the tile
   __syncthreads();
   for (int x = threadIdx.x; x < 6 * T; x += BLOCK) tile[x] = (Acc)0;
@@ -566,10 +614,20 @@ void k_adjoint(AdjArgs<Real> A) {
   } else {
     __syncthreads();
   }
-  if (live) {
+#pragma unroll
+  for (int r = 0; r < APT; ++r) {
+    if (ccr[r] & DEAD_BIT) continue;
+    const int64_t p = pr[r];
+    int i[3], dsh[3];
+    cell_decode(g, ccr[r], i);
+    unwrap(i, dsh);
+    Stencil1<Real> st[3];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) st[a] = stencil1(i[a], (Real)PS::weight(A.p.offs[a][p]));
     bool in = true;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) in = in && (ib[d] - 1 >= t0[d]) && (ib[d] + 1 < t0[d] + ts[d]);
+    for (int d = 0; d < DIM; ++d)
+      in = in && (i[d] + dsh[d] - 1 >= t0[d]) && (i[d] + dsh[d] + 1 < t0[d] + ts[d]);
     const int sy = ts[0], sz = ts[0] * ts[1];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -594,7 +652,7 @@ void k_adjoint(AdjArgs<Real> A) {
         }
       }
       if (in) {
-        const Real fb = tile_coef(Fbar[c], esc);
+        const Real fb = tile_coef(Fbr[r][c], esc);
         const int base = c * T + (bx + dsh[0] - t0[0]) + sy * (by + dsh[1] - t0[1]) +
                          ((DIM == 3) ? sz * (bz + dsh[2] - t0[2]) : 0);
 #pragma unroll
@@ -603,7 +661,7 @@ void k_adjoint(AdjArgs<Real> A) {
           atomic_add_r(tile + base + o, fb * wt[e]);
         }
       } else {
-        const Real fb = Fbar[c];
+        const Real fb = Fbr[r][c];
         Real *dE = A.dEB + c * (int)g.npts;
         const int np0 = g.np[0], np01 = np0 * g.np[1];
         const int base = pad_index(g, bx, by, bz, DIM);

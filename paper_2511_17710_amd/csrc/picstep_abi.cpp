@@ -542,7 +542,7 @@ pic_status bwd(pic_ctx *c, double dt, int32_t K, int32_t m, char *ws, const void
   if (e != hipSuccess) return hipchk(c, e, "backward setup");
   AdjArgs<Real> A{};
   A.g = g;
-  A.sp = species_table(c, dt, BLOCK);
+  A.sp = species_table(c, dt, adj_chunk(c->eb));
   A.EB = reinterpret_cast<const Real *>(c->fields);
   A.dEB = dE;
   A.dt = dt;
@@ -650,7 +650,7 @@ pic_status adjoint_one(pic_ctx *c, double dt, const void *lamJ, const pic_adjoin
   const uint64_t cap = c->capacity;
   AdjArgs<Real> A{};
   A.g = g;
-  A.sp = species_table(c, dt, BLOCK);
+  A.sp = species_table(c, dt, adj_chunk(c->eb));
   A.p = pset_of<Real>(c, c->active);
   A.EB = reinterpret_cast<const Real *>(c->fields);
   A.dEB = static_cast<Real *>(io->dEB);
