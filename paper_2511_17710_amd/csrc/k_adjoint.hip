@@ -30,6 +30,27 @@ __device__ __forceinline__ void corners(const Real *__restrict__ A, int base, in
     c[e] = A[base + (e & 1) + ((e >> 1) & 1) * sy + ((DIM == 3) ? ((e >> 2) & 1) * sz : 0)];
 }
 
+// derivative of a first-order interpolation from the corner values cv along
+// the offsets in x, y (and z); fw: the weights along x, y, z
+template <int DIM, class Real>
+__device__ __forceinline__ void offset_grad(const Real cv[8], const Real fw[3], Real G[3]) {
+  const Real fx = fw[0], fy = fw[1], fz = fw[2];
+  const Real gx = (Real)1 - fx, gy = (Real)1 - fy;
+  if (DIM == 2) {
+    G[0] = gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]);
+    G[1] = gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]);
+    G[2] = (Real)0;
+  } else {
+    const Real gz = (Real)1 - fz;
+    G[0] = gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
+           fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6]));
+    G[1] = gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
+           fz * (gx * (cv[6] - cv[4]) + fx * (cv[7] - cv[5]));
+    G[2] = gy * (gx * (cv[4] - cv[0]) + fx * (cv[5] - cv[1])) +
+           fy * (gx * (cv[6] - cv[2]) + fx * (cv[7] - cv[3]));
+  }
+}
+
 // copy ncomp components of a padded global array over the box [o, o + s) of
 // (unwrapped) cells into LDS, component-major, x fastest; Cartesian grids
 // take the periodic image of points outside the padded lattice, curvilinear
@@ -505,6 +526,31 @@ void k_adjoint(AdjArgs<Real> A) {
     ft.ts[a] = ts[a];
   }
 
+  // FP32: each component's offset derivative is formed from the corner
+  // values the interpolation reads and kept in registers until dL/dF is
+  // known; FP64 (two particles per thread) reads the corners again instead,
+  // which keeps its occupancy
+  constexpr bool FUSED = sizeof(Real) == 4;
+  // corner values of component c around a particle (LDS copy or global
+  // memory) and its weights along x, y, z
+  auto stencil_corners = [&](int c, const Stencil1<Real> *st, const int *dsh, Real cv[8],
+                             Real fw[3]) {
+    const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
+    const int bx = sx ? st[0].bh : st[0].b0;
+    const int by = sy2 ? st[1].bh : st[1].b0;
+    const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
+    fw[0] = sx ? st[0].fh : st[0].f0;
+    fw[1] = sy2 ? st[1].fh : st[1].f0;
+    fw[2] = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
+    if (stage)
+      corners<DIM, Real>(lds.f + c * T,
+                         (bx + dsh[0] - t0[0]) + ft.sy * (by + dsh[1] - t0[1]) +
+                             ((DIM == 3) ? ft.sz * (bz + dsh[2] - t0[2]) : 0),
+                         ft.sy, ft.sz, cv);
+    else
+      corners<DIM, Real>(A.EB + c * (int)g.npts, pad_index(g, bx, by, bz, DIM), g.np[0],
+                         g.np[0] * g.np[1], cv);
+  };
   Real Fbr[APT][6];
   float bmax = 0.0f;
 #pragma unroll
@@ -517,21 +563,25 @@ void k_adjoint(AdjArgs<Real> A) {
     cell_decode(g, ccr[r], i);
     unwrap(i, dsh);
     Real *Fbar = Fbr[r];
-    Stencil1<Real> st[3];
     OffT<Real> q[3] = {(OffT<Real>)0, (OffT<Real>)0, (OffT<Real>)0};
     Real d[3] = {0, 0, 0};
+    Real F[6], G[FUSED ? 6 : 1][3];
+    Stencil1<Real> st[3];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       q[a] = A.p.offs[a][p];
       d[a] = (Real)PS::weight(q[a]);
       st[a] = stencil1(i[a], d[a]);
     }
-    // ---------------- forward recompute of step 3 (interpolation)
-    Real F[6];
-    if (stage)
-      interp6_tile<DIM, Real>(ft, dsh, st, F);
-    else
-      interp6<DIM, Real>(A.EB, g, st, F);
+    // ---------------- forward recompute of step 3 (interpolation: the
+    // forward kernel's expression on the same corner values)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      Real cv[8], fw[3];
+      stencil_corners(c, st, dsh, cv, fw);
+      F[c] = gather_at<DIM, Real>(cv, 0, 2, 4, fw[0], fw[1], fw[2]);
+      if constexpr (FUSED) offset_grad<DIM, Real>(cv, fw, G[c]);
+    }
     // dL/dJ from the LDS copy (box frame) or from global memory
     BoxView<Real> LJ;
     if (stage) {
@@ -565,36 +615,19 @@ void k_adjoint(AdjArgs<Real> A) {
     // the offset derivative of the interpolation weights
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-      const int sx = kStag[c][0], sy2 = kStag[c][1], sz2 = kStag[c][2];
-      const int bx = sx ? st[0].bh : st[0].b0;
-      const int by = sy2 ? st[1].bh : st[1].b0;
-      const int bz = (DIM == 3) ? (sz2 ? st[2].bh : st[2].b0) : 0;
-      const Real fx = sx ? st[0].fh : st[0].f0;
-      const Real fy = sy2 ? st[1].fh : st[1].f0;
-      const Real fz = (DIM == 3) ? (sz2 ? st[2].fh : st[2].f0) : (Real)0;
-      Real cv[8];
-      if (stage)
-        corners<DIM, Real>(lds.f + c * T, (bx + dsh[0] - t0[0]) + ft.sy * (by + dsh[1] - t0[1]) +
-                                              ((DIM == 3) ? ft.sz * (bz + dsh[2] - t0[2]) : 0),
-                           ft.sy, ft.sz, cv);
-      else
-        corners<DIM, Real>(A.EB + c * (int)g.npts, pad_index(g, bx, by, bz, DIM), g.np[0],
-                           g.np[0] * g.np[1], cv);
-      const Real gx = (Real)1 - fx, gy = (Real)1 - fy;
       const Real fb = Fbar[c];
       bmax = fmaxf(bmax, fabsf((float)fb));
-      if (DIM == 2) {
-        ab[0] += fb * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2]));
-        ab[1] += fb * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1]));
+      Real gc[3];
+      if constexpr (FUSED) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gc[a] = G[c][a];
       } else {
-        const Real gz = (Real)1 - fz;
-        ab[0] += fb * (gz * (gy * (cv[1] - cv[0]) + fy * (cv[3] - cv[2])) +
-                       fz * (gy * (cv[5] - cv[4]) + fy * (cv[7] - cv[6])));
-        ab[1] += fb * (gz * (gx * (cv[2] - cv[0]) + fx * (cv[3] - cv[1])) +
-                       fz * (gx * (cv[6] - cv[4]) + fx * (cv[7] - cv[5])));
-        ab[2] += fb * (gy * (gx * (cv[4] - cv[0]) + fx * (cv[5] - cv[1])) +
-                       fy * (gx * (cv[6] - cv[2]) + fx * (cv[7] - cv[3])));
+        Real cv[8], fw[3];
+        stencil_corners(c, st, dsh, cv, fw);
+        offset_grad<DIM, Real>(cv, fw, gc);
       }
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) ab[a] += fb * gc[a];
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) A.lam_d[a][p] = ab[a];
