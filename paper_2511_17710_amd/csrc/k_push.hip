@@ -386,7 +386,15 @@ void k_push(StepArgs<Real> A) {
   if (!locate_chunk<SPARSE, PPT>(A.sp, s, c0, A.perm != nullptr || A.serial, A.block_base))
     return;  // uniform over the block
   const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
-  const int64_t first = c0 + (int64_t)threadIdx.x * ppt;
+  // a lane's ppt particles are consecutive (vector loads), and neighbouring
+  // lanes 4 particles apart whatever ppt (with ppt < 4, 4/ppt waves
+  // interleave): a wave's lanes then share each cell's field reads as
+  // broadcasts and spread the deposit's same-address atomics alike (lanes 2
+  // apart in FP64: 4.15 -> 4.09 ms per step; 8 apart in FP32: 2.22 -> 2.33)
+  const int lsh = (ppt == 4) ? 0 : ((ppt == 2) ? 1 : 2);
+  const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
+  const int slot = ((wv >> lsh) << (6 + lsh)) + (ln << lsh) + (wv & ((1 << lsh) - 1));
+  const int64_t first = c0 + (int64_t)slot * ppt;
   const int cnt = (int)max((int64_t)0, min((int64_t)ppt, A.sp.n[s] - first));
   const int64_t p0 = A.sp.off[s] + first;
 
