@@ -387,11 +387,14 @@ void k_push(StepArgs<Real> A) {
     return;  // uniform over the block
   const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
   // a lane's ppt particles are consecutive (vector loads), and neighbouring
-  // lanes 4 particles apart whatever ppt (with ppt < 4, 4/ppt waves
-  // interleave): a wave's lanes then share each cell's field reads as
-  // broadcasts and spread the deposit's same-address atomics alike (lanes 2
-  // apart in FP64: 4.15 -> 4.09 ms per step; 8 apart in FP32: 2.22 -> 2.33)
-  const int lsh = (ppt == 4) ? 0 : ((ppt == 2) ? 1 : 2);
+  // lanes 4 particles apart for ppt 4 and 2 (two waves interleave): a wave's
+  // lanes then share each cell's field reads as broadcasts and spread the
+  // deposit's same-address atomics alike (lanes 2 apart in FP64: 4.15 ->
+  // 4.09 ms per step; 8 apart in FP32: 2.22 -> 2.33).  ppt 1 (below 3
+  // particles per cell) keeps neighbouring lanes on neighbouring particles:
+  // those lie in different cells anyway, and spreading them slowed the
+  // sparsest species by 15 %
+  const int lsh = (ppt == 2) ? 1 : 0;
   const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
   const int slot = ((wv >> lsh) << (6 + lsh)) + (ln << lsh) + (wv & ((1 << lsh) - 1));
   const int64_t first = c0 + (int64_t)slot * ppt;
