@@ -19,6 +19,18 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t nblk) {
   return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Segments of seg consecutive chunks dealt to the XCDs round robin: XCD x
+// takes segments x, x + 8, x + 16, ... in turn (blocks b = 8k + x, k-th
+// block of XCD x), so the XCDs together sweep the chunks in order while each
+// L2 serves runs of seg neighbouring chunks; the blocks past the last whole
+// round of 8 segments keep the plain order (a bijection on [0, nblk)).
+__device__ __forceinline__ int64_t xcd_segment_chunk(int64_t b, int64_t nblk, int64_t seg) {
+  const int64_t whole = nblk / (NXCD * seg) * (NXCD * seg);
+  if (b >= whole) return b;
+  const int64_t x = b % NXCD, k = b / NXCD;
+  return ((k / seg) * NXCD + x) * seg + k % seg;
+}
+
 // largest s with s^dim <= vals
 constexpr int tile_side(int vals, int dim) {
   int s = 1;

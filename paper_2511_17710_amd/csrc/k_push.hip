@@ -125,16 +125,23 @@ __device__ __forceinline__ void store_n(T *p, int cnt, const T v[N]) {
 // ---------------------------------------------------------------- block -> chunk
 // XCD-aware order (each XCD's L2 keeps the fields and current around its
 // neighbouring chunks), except on the step that reads through a sort's
-// permutation (plain): there the blocks in flight on all XCDs sweep about
-// one plane of bricks at a time, so the particles that came from the plane
-// before are read while it is still cached; under the XCD order they were
-// last touched many L2 capacities earlier (push 3.4 -> 3.2 ms on that step).
+// permutation: there the blocks in flight on all XCDs sweep about one plane
+// of bricks at a time, so the particles that came from the plane before are
+// read while it is still cached (under the XCD order they were last touched
+// many L2 capacities earlier: push 3.4 -> 3.2 ms on that step), and the
+// chunks are dealt to the XCDs in segments of 32 (neighbouring chunks read
+// much the same source lines, which one L2 then serves: 3.2 -> 3.05 ms).
+// The debug launch with one block in flight takes the plain order.
+constexpr int64_t GATHER_SEGMENT = 32;
 template <bool SPARSE, int PPT>
 __device__ __forceinline__ bool locate_chunk(const SpeciesTable &sp, int &s, int64_t &c0,
-                                             bool plain, int64_t base) {
+                                             bool gather, bool serial, int64_t base) {
   // blk0[MAXSP] = all blocks
   const int64_t bid = base + (int64_t)blockIdx.x;
-  const int64_t b = plain ? bid : xcd_chunk(bid, sp.blk0[MAXSP]);
+  const int64_t nb = sp.blk0[MAXSP];
+  const int64_t b = serial   ? bid
+                    : gather ? xcd_segment_chunk(bid, nb, GATHER_SEGMENT)
+                             : xcd_chunk(bid, nb);
   s = 0;
 #pragma unroll
   for (int t = 1; t < MAXSP; ++t)
@@ -383,7 +390,7 @@ void k_push(StepArgs<Real> A) {
   int s;
   int64_t c0;
   constexpr int PPT = push_ppt<Real>();
-  if (!locate_chunk<SPARSE, PPT>(A.sp, s, c0, A.perm != nullptr || A.serial, A.block_base))
+  if (!locate_chunk<SPARSE, PPT>(A.sp, s, c0, A.perm != nullptr, A.serial, A.block_base))
     return;  // uniform over the block
   const int ppt = SPARSE ? A.sp.ppt[s] : PPT;
   // a lane's ppt particles are consecutive (vector loads), and neighbouring
