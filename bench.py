@@ -208,6 +208,48 @@ def run_adjoint(prec, log, name="cart3d_64_adj"):
     return res
 
 
+def run_fields(name, prec, log, calls=20):
+    """The field solver on a workload's grid: Faraday (advance B), Ampere
+    (advance E with the current) and one pass of the current filter, each
+    timed over `calls` launches with HIP events on the library's stream;
+    algorithmic bytes per updated lattice point: Faraday reads E and B and
+    writes B (9 values), Ampere reads B, J and E and writes E (12), a filter
+    pass reads and writes J (6)."""
+    import torch
+
+    from paper_2511_17710_amd import picstep as P
+    from paper_2511_17710_amd import workloads as W
+    wl = W.by_name(name)
+    ctx = P.from_workload(wl, prec=prec)
+    dt = ctx.timestep_from_cfl(wl.cfl)
+    ctx.push_deposit(dt, 1)  # a current to filter and to couple
+    b = 4 if prec == "f32" else 8
+    n = list(wl.n[:wl.dim])
+    pts = int(np.prod([v + (1 if wl.geom != "cart" else 0) for v in n]))
+    s = ctx.stream
+    ops = (("faraday", lambda: ctx.fields_advance_b(0.5 * dt), 9),
+           ("ampere", lambda: ctx.fields_advance_e(dt), 12),
+           ("filter", lambda: ctx.current_filter(1), 6))
+    res = dict(workload=wl.name, updated_points=pts)
+    for tag, fn, vals in ops:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(calls):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / calls
+        ach = vals * b * pts / (ms * 1e-3) / 1e9
+        res[tag] = dict(ms=round(ms, 4), bytes_per_point=vals * b, achieved=round(ach, 1),
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4))
+    log(f"[bench] fields {name} {prec}: {res}")
+    del ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, sample_per_species, steps, log):
     """FP64 CPU reference (single thread) on the first particles of each species."""
     from oracle import oracle as O
@@ -244,6 +286,8 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true")
     ap.add_argument("--skip-axisymmetric", action="store_true",
                     help="leave out the 1024x512 and 2048x1024 axisymmetric rows")
+    ap.add_argument("--skip-fields", action="store_true",
+                    help="leave out the field-solver rows")
     ap.add_argument("--skip-sweep", action="store_true",
                     help="leave out the particle-count sweep on the default grid")
     ap.add_argument("--sort-every", type=int, default=None,
@@ -309,7 +353,13 @@ def main():
     adj = None
     if not args.skip_adjoint:
         adj = {p: run_adjoint(p, log) for p in (("f32",) if args.skip_fp64 else ("f32", "f64"))}
-    emit(args, meta, dict(r32=r32, r64=r64, sweep=sweep, cpu=cpu, axi=axi, adj=adj))
+    fields = None
+    if not args.skip_fields and args.workload == "cart3d_128":
+        precs = ("f32",) if args.skip_fp64 else ("f32", "f64")
+        fields = {name: {p: run_fields(name, p, log) for p in precs}
+                  for name in ("cart3d_128", "qsph_2048x1024")}
+    emit(args, meta, dict(r32=r32, r64=r64, sweep=sweep, cpu=cpu, axi=axi, adj=adj,
+                          fields=fields))
 
 
 def emit(args, meta, f):
@@ -356,6 +406,8 @@ def emit(args, meta, f):
                                                         push_ms_avg=round(r32["push_ms_avg"], 4))]
     if f["adj"]:
         out["adjoint"] = f["adj"]
+    if f.get("fields"):
+        out["field_solver"] = f["fields"]
     if f["cpu"]:
         out["cpu_baseline"] = f["cpu"]
     print(json.dumps(out), flush=True)
