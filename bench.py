@@ -8,8 +8,12 @@ particles per cell each (67,108,864 particles), Maxwell-Juttner theta=1 with a
 
 Prints one JSON line: ns per particle per step of the FP32 library (value),
 the FP64 form beside it, the roofline of the fused particle-step kernel
-(algorithmic HBM bytes per launch over its HIP-event duration), and the FP64
-CPU reference timed on a bounded sample of the same workload.
+(algorithmic HBM bytes per launch over its HIP-event duration, and the
+calibrated counter traffic of the committed profile while it matches the
+sources), the axisymmetric workloads, a particle-count sweep, the
+checkpointed adjoint with the reverse-step kernel's roofline, the field
+solver's kernels, and the FP64 CPU reference timed on a bounded sample of
+the same workload.
 """
 import argparse
 import json
