@@ -2,9 +2,10 @@
 // (arXiv 2511.17710, Sec. 2.3 steps 3-8), one launch for all species.
 //
 // A block owns a chunk of consecutive particles of one species (4 per
-// thread, loaded with 16-byte vector accesses, or fewer for sparse species;
-// through the permutation of a sort on the step that follows it).  Particles are kept in brick order by the
-// per-cell sort, so the chunk's cells form a compact box.  One LDS buffer
+// thread in FP32, 2 in FP64, loaded with 16-byte vector accesses, or fewer
+// for sparse species; read through the permutation of a sort on the step
+// that follows it).  Particles are kept in brick order by the per-cell sort,
+// so the chunk's cells form a compact box.  One LDS buffer
 // serves in turn as the block's copy of the fields over that box (when it
 // fits) for the push pass, and as the block's current tile over the box
 // (plus the stencil halo) for the deposit pass: exact 64-bit fixed-point
