@@ -29,6 +29,8 @@ struct GridConst {
   int64_t npts;
   double dx[3];                 // Cartesian cell sizes (1 for unused dims)
   double inv_dx[3];             // 1 / dx
+  float dxf[3], inv_dxf[3];     // the same rounded to FP32 on the host (FP32 kernels
+                                // read them from scalar registers, no conversion per use)
   double rmin, dr, dth;         // spherical: r = rmin + x1 dr, theta = x2 dth
   double Rmin, dR, dT, r0, vt;  // quasi-spherical: r = r0 + exp(Rmin + x1 dR), T = x2 dT
   int fp64_cells;               // FP32 curvilinear: cells near theta=0,pi and r_min done in FP64
@@ -72,6 +74,7 @@ struct SpeciesTable {
   int64_t blk0[MAXSP + 1]; // prefix of block counts over species
   int ppt[MAXSP];          // fused step kernel: particles per thread (1, 2 or 4)
   double k[MAXSP];         // q dt / (2 m rho0)
+  float kf[MAXSP];         // k rounded to FP32 on the host
   double qdt[MAXSP];       // q / dt
   int pusher[MAXSP];       // 0 Boris, 1 Vay, +2 guiding-centre hybrid
   double gca_e_ovr[MAXSP]; // hybrid: guiding centre while |E| < e_ovr |B| ...
@@ -88,6 +91,7 @@ struct StepArgs {
   const Real *EB;
   Real *J;
   double dt;
+  float dtf;               // dt rounded to FP32 on the host
   int write_prev;
   int deposit;             // 0: move only (adjoint recompute)
   int32_t *stats;          // [0]: blocks, [1]: blocks that deposited with global atomics

@@ -216,12 +216,12 @@ __device__ __forceinline__ void cart_particle_rev(const AdjArgs<Real> &A, int s,
   using PS = Pos<Real>;
   const GridConst &g = A.g;
   const Real u0[3] = {A.p.u[0][p], A.p.u[1][p], A.p.u[2][p]};
-  const Real k = (Real)A.sp.k[s];
+  const Real k = konst<Real>(A.sp.k[s], A.sp.kf[s]);
   const Real dtr = (Real)A.dt;
   Real E[3], B[3], sc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    sc[a] = (a < DIM) ? (Real)g.dx[a] : (Real)1;
+    sc[a] = (a < DIM) ? konst<Real>(g.dx[a], g.dxf[a]) : (Real)1;
     E[a] = F[a] * sc[a];
     B[a] = F[3 + a] * sc[a];
   }
@@ -285,7 +285,7 @@ __device__ __forceinline__ void axi_particle_rev(const AdjArgs<Real> &A, int s, 
                                                  Real Fb[6], Real ab[3]) {
   using PS = Pos<Real>;
   const GridConst &g = A.g;
-  const Real k = (Real)A.sp.k[s];
+  const Real k = konst<Real>(A.sp.k[s], A.sp.kf[s]);
   const Real phi = A.p.phi[p];
   // ---- forward recompute (the operations of axi_particle)
   const CT x1 = (CT)i[0] + (CT)d1;

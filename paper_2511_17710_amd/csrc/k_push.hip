@@ -219,17 +219,17 @@ __device__ __forceinline__ int32_t cart_push(const StepArgs<Real> &A, const Fiel
   Real E[3], B[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const Real sc = (a < DIM) ? (Real)g.dx[a] : (Real)1;
+    const Real sc = (a < DIM) ? konst<Real>(g.dx[a], g.dxf[a]) : (Real)1;
     E[a] = F[a] * sc;
     B[a] = F[3 + a] * sc;
   }
   if (PUSHERS)
-    push_momentum<Real>(A.sp, s, (Real)A.sp.k[s], A.dt, E, B, u);
+    push_momentum<Real>(A.sp, s, konst<Real>(A.sp.k[s], A.sp.kf[s]), A.dt, E, B, u);
   else
-    boris((Real)A.sp.k[s], E, B, u);
+    boris(konst<Real>(A.sp.k[s], A.sp.kf[s]), E, B, u);
   // move (steps 6-7): offsets advance by dt u / (gamma Delta)
   const Real gi = rsqrt_r((Real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-  const Real dtr = (Real)A.dt;
+  const Real dtr = konst<Real>(A.dt, A.dtf);
   int m[3] = {0, 0, 0};
   int inew[3] = {i[0], i[1], i[2]};
 #pragma unroll

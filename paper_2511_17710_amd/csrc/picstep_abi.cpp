@@ -163,6 +163,7 @@ SpeciesTable species_table(const pic_ctx *c, double dt, int64_t per_block) {
     t.n[s] = (int64_t)c->cnt[s];
     t.blk0[s + 1] = t.blk0[s] + (t.n[s] + per_block - 1) / per_block;
     t.k[s] = c->q[s] * dt / (2.0 * c->m[s] * c->d.rho0);
+    t.kf[s] = (float)t.k[s];
     t.qdt[s] = c->q[s] / dt;
     t.pusher[s] = c->pusher[s];
     t.gca_e_ovr[s] = c->gca_e_ovr[s];
@@ -356,6 +357,7 @@ pic_status do_step(pic_ctx *c, double dt, bool write_prev, bool dep = true) {
   a.EB = reinterpret_cast<const Real *>(c->fields);
   a.J = reinterpret_cast<Real *>(c->current);
   a.dt = dt;
+  a.dtf = (float)dt;
   a.write_prev = write_prev ? 1 : 0;
   a.deposit = dep ? 1 : 0;
   a.stats = c->timing ? reinterpret_cast<int32_t *>(c->scratch + c->s_stats) : nullptr;
@@ -714,6 +716,8 @@ pic_status pic_grid_init(const pic_grid_desc *desc, pic_ctx **out) {
     g.np[a] = a < d.dim ? d.n[a] + 2 * NG : 1;
     g.dx[a] = (d.geom == PIC_CART && a < d.dim) ? (d.hi[a] - d.lo[a]) / d.n[a] : 1.0;
     g.inv_dx[a] = 1.0 / g.dx[a];
+    g.dxf[a] = (float)g.dx[a];
+    g.inv_dxf[a] = (float)g.inv_dx[a];
   }
   g.npts = (int64_t)g.np[0] * g.np[1] * g.np[2];
   if (6 * g.npts >= (int64_t(1) << 31)) {  // device index math is 32-bit

@@ -347,8 +347,18 @@ __device__ __forceinline__ void boris_rev(Real k, const BorisRec<Real> &R, const
 // (it matches the reference's rounding).  The forward and the adjoint
 // recompute share this routine, so both take the same step.
 __device__ __forceinline__ float cart_disp(const GridConst &g, int a, float dt, float u, float gi) {
-  return dt * u * gi * (float)g.inv_dx[a];
+  return dt * u * gi * g.inv_dxf[a];
 }
+
+// A double constant in the storage precision: its host-rounded FP32 copy in
+// FP32 contexts (equal to a conversion on the device, both round to
+// nearest, but read from scalar registers), the double itself in FP64 ones.
+template <class Real>
+__device__ __forceinline__ Real konst(double d, float f);
+template <>
+__device__ __forceinline__ float konst<float>(double, float f) { return f; }
+template <>
+__device__ __forceinline__ double konst<double>(double d, float) { return d; }
 __device__ __forceinline__ double cart_disp(const GridConst &g, int a, double dt, double u,
                                             double gi) {
   return dt * u * gi / g.dx[a];
@@ -724,7 +734,7 @@ __device__ __forceinline__ void axi_particle(const GridConst &g, const SpeciesTa
                                              double dt, int i1, int i2, D d1, D d2, Real phi,
                                              const Real F[6], Real u[3], CT &dx1, CT &dx2,
                                              CT &dphi) {
-  const Real k = (Real)sp.k[s];
+  const Real k = konst<Real>(sp.k[s], sp.kf[s]);
   const CT x1 = (CT)i1 + (CT)d1;
   const CT x2 = (CT)i2 + (CT)d2;
   const AxiMetric<CT> M = axi_metric<GEOM, CT>(g, x1, x2);
