@@ -337,6 +337,71 @@ __global__ __launch_bounds__(FX *FY) void k_filter(GridConst g, const Real *in, 
   out[q] = (Real)acc;
 }
 
+// The filter pass on 3D periodic Cartesian grids as a sweep along z: a
+// thread owns an (x, y) column of one component over a run of planes,
+// forms each plane's 3x3 weighted sum once (9 reads) and combines three
+// consecutive plane sums per output (the weights factor per dimension), so
+// an output costs 9 reads instead of 27.  Columns outside the updated range
+// (ghosts) and ghost planes are copied.  z of the launch grid: component x
+// run of ZRUN planes.
+constexpr int ZRUN = 16;
+template <class Real>
+__global__ __launch_bounds__(FX *FY) void k_filter_zsweep(GridConst g, const Real *in, Real *out,
+                                                          int nrun) {
+  const int ip = (int)(blockIdx.x * FX + threadIdx.x), jp = (int)(blockIdx.y * FY + threadIdx.y);
+  if (ip >= g.np[0] || jp >= g.np[1]) return;
+  const int c = (int)blockIdx.z / nrun, run = (int)blockIdx.z - c * nrun;
+  const int np2 = g.np[2];
+  const int kp0 = run * ZRUN, kp1 = min(np2, kp0 + ZRUN);
+  const int s1 = g.np[0], s2 = g.np[0] * g.np[1];
+  const Real *src = in + (int64_t)c * g.npts;
+  Real *dst = out + (int64_t)c * g.npts;
+  const int col = ip + s1 * jp;
+  const int i = ip - NG, j = jp - NG;
+  if (i < 0 || i >= g.n[0] || j < 0 || j >= g.n[1]) {  // a ghost column: copied
+    for (int kp = kp0; kp < kp1; ++kp) dst[col + s2 * kp] = src[col + s2 * kp];
+    return;
+  }
+  // x and y neighbours of the column, wrapped
+  const int xm = (i == 0) ? g.n[0] - 1 : -1, xp = (i == g.n[0] - 1) ? 1 - g.n[0] : 1;
+  const int ym = ((j == 0) ? g.n[1] - 1 : -1) * s1, yp = ((j == g.n[1] - 1) ? 1 - g.n[1] : 1) * s1;
+  const int n2 = g.n[2];
+  // weighted 3x3 sum of plane k (wrapped into [0, n2))
+  auto plane = [&](int k) {
+    k += (k < 0) ? n2 : 0;
+    k -= (k >= n2) ? n2 : 0;
+    const Real *b = src + col + s2 * (k + NG);
+    const Real *rows[3] = {b + ym, b, b + yp};
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double wy = (r == 1) ? 0.5 : 0.25;
+      acc += wy * 0.25 * (double)rows[r][xm];
+      acc += wy * 0.5 * (double)rows[r][0];
+      acc += wy * 0.25 * (double)rows[r][xp];
+    }
+    return acc;
+  };
+  double pm = 0.0, pc = 0.0;
+  bool primed = false;
+  for (int kp = kp0; kp < kp1; ++kp) {
+    const int k = kp - NG;
+    if (k < 0 || k >= n2) {  // a ghost plane: copied
+      dst[col + s2 * kp] = src[col + s2 * kp];
+      continue;
+    }
+    if (!primed) {
+      pm = plane(k - 1);
+      pc = plane(k);
+      primed = true;
+    }
+    const double pn = plane(k + 1);
+    dst[col + s2 * kp] = (Real)(0.25 * pm + 0.5 * pc + 0.25 * pn);
+    pm = pc;
+    pc = pn;
+  }
+}
+
 dim3 solver_grid(const GridConst &g) {
   const unsigned e0 = (unsigned)(g.n[0] + (g.geom != 0 ? 1 : 0));
   const unsigned e1 = (unsigned)(g.n[1] + (g.geom != 0 ? 1 : 0));
@@ -376,6 +441,13 @@ hipError_t launch_ampere(const GridConst &g, Real *EB, const Real *J, double dt,
 
 template <class Real>
 hipError_t launch_filter(const GridConst &g, const Real *in, Real *out, hipStream_t s) {
+  if (g.geom == 0 && g.dim == 3) {
+    const int nrun = (g.np[2] + ZRUN - 1) / ZRUN;
+    const dim3 grid((unsigned)((g.np[0] + FX - 1) / FX), (unsigned)((g.np[1] + FY - 1) / FY),
+                    (unsigned)(3 * nrun));
+    hipLaunchKernelGGL(k_filter_zsweep<Real>, grid, dim3(FX, FY), 0, s, g, in, out, nrun);
+    return hipGetLastError();
+  }
   const int np2 = (int)(g.npts / ((int64_t)g.np[0] * g.np[1]));
   const dim3 grid((unsigned)((g.np[0] + FX - 1) / FX), (unsigned)((g.np[1] + FY - 1) / FY),
                   (unsigned)(3 * np2));
