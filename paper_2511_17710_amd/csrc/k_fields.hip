@@ -5,7 +5,8 @@
 //
 // These are streaming stencil sweeps over the field arrays (a few bytes per
 // lattice point against the tens per particle of the particle step): one
-// thread per lattice point, x fastest so that neighbouring lanes read
+// thread per lattice point (the filter of 3D periodic grids: per column run
+// along z), x fastest so that neighbouring lanes read
 // neighbouring addresses, every component of the point handled by its thread,
 // geometry and dimension fixed at compile time; metric factors are evaluated
 // on the fly in FP64 (they are never stored, as in the paper), once per row
