@@ -75,10 +75,39 @@ __device__ __forceinline__ MetricCol metric_col(const GridConst &g, double x2) {
   return {h2f, st};
 }
 
+// The solver kernels take one thread per lattice point on a 2D (3D) launch
+// grid: x (the fastest index) over blocks of FX lanes, y over FY rows per
+// block, z over planes, so a point's indices need no division.
+constexpr int FX = 64, FY = 4;
+
+// A block's metric rows x1 = i0 - 1/2 + t/2 and columns x2 = j0 - 1/2 + t/2
+// ((i0, j0) its first point), every half step its threads' stencils touch,
+// evaluated once per block in LDS (an exponential per row and a sine per
+// column on the quasi-spherical grid, against one per stencil point).
+template <int GEOM>
+struct MetricTables {
+  static constexpr int NR = GEOM != 0 ? 2 * FX + 4 : 1, NC = GEOM != 0 ? 2 * FY + 4 : 1;
+  MetricRow r[NR];
+  MetricCol c[NC];
+};
+template <int GEOM>
+__device__ __forceinline__ void fill_metric_tables(const GridConst &g, MetricTables<GEOM> &T) {
+  if constexpr (GEOM != 0) {
+    constexpr int NR = MetricTables<GEOM>::NR, NC = MetricTables<GEOM>::NC;
+    const int tid = (int)(threadIdx.x + FX * threadIdx.y);
+    const double x0 = (double)(blockIdx.x * FX) - 0.5, y0 = (double)(blockIdx.y * FY) - 0.5;
+    if (tid < NR)
+      T.r[tid] = metric_row<GEOM>(g, x0 + 0.5 * tid);
+    else if (tid < NR + NC)
+      T.c[tid - NR] = metric_col<GEOM>(g, y0 + 0.5 * (tid - NR));
+    __syncthreads();
+  }
+}
+
 // The lattice around a thread's point (i, j, k): covariant components and
 // sqrt(h) at Yee points addressed relative to it, the metric from the rows
-// x1 = i + (q - 1)/2 and columns x2 = j + (q - 1)/2, q = 0..3 (the
-// compiler keeps the ones a kernel uses).
+// x1 = i + (q - 1)/2 and columns x2 = j + (q - 1)/2, q = 0..3, of the
+// block's tables (the compiler keeps the ones a kernel uses).
 template <int GEOM, int DIM, class Real>
 struct FieldView {
   const GridConst &g;
@@ -86,13 +115,14 @@ struct FieldView {
   int i, j, k;
   MetricRow R[4];
   MetricCol C[4];
-  __device__ __forceinline__ FieldView(const GridConst &g_, const Real *A_, int i_, int j_, int k_)
+  __device__ __forceinline__ FieldView(const GridConst &g_, const Real *A_, int i_, int j_, int k_,
+                                       const MetricTables<GEOM> &T)
       : g(g_), A(A_), i(i_), j(j_), k(k_) {
     if constexpr (GEOM != 0) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        R[q] = metric_row<GEOM>(g, i + 0.5 * (q - 1));
-        C[q] = metric_col<GEOM>(g, j + 0.5 * (q - 1));
+        R[q] = T.r[2 * threadIdx.x + q];
+        C[q] = T.c[2 * threadIdx.y + q];
       }
     }
   }
@@ -123,11 +153,6 @@ __device__ __forceinline__ bool axis_node(const GridConst &g, int j) {
   return GEOM != 0 && (j == 0 || j == g.n[1]);
 }
 
-// The solver kernels take one thread per lattice point on a 2D (3D) launch
-// grid: x (the fastest index) over blocks of FX lanes, y over FY rows per
-// block, z over planes, so a point's indices need no division.
-constexpr int FX = 64, FY = 4;
-
 // the extents of the points the solver updates (any component)
 template <int GEOM, int DIM>
 __device__ __forceinline__ bool solver_point(const GridConst &g, int &i, int &j, int &k) {
@@ -142,9 +167,11 @@ __device__ __forceinline__ bool solver_point(const GridConst &g, int &i, int &j,
 // axis nodes stays 0 (Sec. 2.6)
 template <int GEOM, int DIM, class Real>
 __global__ __launch_bounds__(FX *FY) void k_faraday(GridConst g, Real *EB, double f) {
+  __shared__ MetricTables<GEOM> mt;
+  fill_metric_tables<GEOM>(g, mt);  // every thread of the block, before any returns
   int i, j, k;
   if (!solver_point<GEOM, DIM>(g, i, j, k)) return;
-  const FieldView<GEOM, DIM, Real> V(g, EB, i, j, k);
+  const FieldView<GEOM, DIM, Real> V(g, EB, i, j, k, mt);
   constexpr bool d3 = DIM == 3;
   const int npts = (int)g.npts;
   const int at = pad_index(g, i, j, k, DIM);
@@ -192,9 +219,11 @@ __device__ __forceinline__ double polar_area(const GridConst &g, double x1) {
 template <int GEOM, int DIM, class Real>
 __global__ __launch_bounds__(FX *FY) void k_ampere(GridConst g, Real *EB, const Real *J, double dt,
                                                   double coupling) {
+  __shared__ MetricTables<GEOM> mt;
+  fill_metric_tables<GEOM>(g, mt);  // every thread of the block, before any returns
   int i, j, k;
   if (!solver_point<GEOM, DIM>(g, i, j, k)) return;
-  const FieldView<GEOM, DIM, Real> V(g, EB, i, j, k);
+  const FieldView<GEOM, DIM, Real> V(g, EB, i, j, k, mt);
   constexpr bool d3 = DIM == 3;
   const int npts = (int)g.npts;
   const int pt = pad_index(g, i, j, k, DIM);
