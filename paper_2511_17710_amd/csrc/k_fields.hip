@@ -9,9 +9,9 @@
 // along z), x fastest so that neighbouring lanes read
 // neighbouring addresses, every component of the point handled by its thread,
 // geometry and dimension fixed at compile time; metric factors are evaluated
-// on the fly in FP64 (they are never stored, as in the paper), once per row
-// and column a thread's stencil touches; values are combined in FP64 and
-// rounded once to the storage precision.
+// on the fly in FP64 (they are never stored between calls, as in the
+// paper), once per row and column of a block's stencils, in LDS; values are
+// combined in FP64 and rounded once to the storage precision.
 #include "step_device.h"
 
 namespace picstep {
