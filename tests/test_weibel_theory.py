@@ -51,3 +51,21 @@ def test_reference_loop_grows_the_filamentation_mode_at_the_theoretical_rate():
     theory = filamentation_growth(2 * np.pi * mode / nx, wp, ub) / wp
     assert theory == pytest.approx(weibel_max_rate(wp, ub) / wp, rel=0.03)
     assert rate == pytest.approx(theory, rel=0.05), (rate, theory)
+
+
+def test_quiet_start_setup():
+    """The two beams sit on the same positions with opposite four-velocities
+    (no current anywhere at the start), stream along +-z at u_b, and their
+    weights give wp^2 = 4 pi (weight per unit volume)."""
+    wp, ub, nx, ny, ppc = 0.1, 0.5, 16, 2, 8
+    grid, (a, b) = setup(nx=nx, ny=ny, ppc=ppc, wp=wp, ub=ub, temp=1e-6)
+    np.testing.assert_array_equal(a["cell"], b["cell"])
+    np.testing.assert_array_equal(a["offs"], b["offs"])
+    np.testing.assert_array_equal(a["u"], -b["u"])
+    assert abs(a["u"][:, 2].mean() - ub) < 1e-3 and np.abs(a["u"][:, :2]).max() < 1e-2
+    w_total = a["w"].sum() + b["w"].sum()
+    assert 4 * np.pi * w_total / (nx * ny) == pytest.approx(wp * wp, rel=1e-12)
+    EB = seed_by(nx, ny, 3, 1e-6, pad=2)
+    assert np.count_nonzero(EB[[0, 1, 2, 3, 5]]) == 0
+    x = np.arange(nx + 4) - 2 + 0.5
+    np.testing.assert_allclose(EB[4, 0, 0], 1e-6 * np.sin(2 * np.pi * 3 * x / nx))
